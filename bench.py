@@ -1,0 +1,177 @@
+"""Benchmark of the diffraction hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+One step = one angular-spectrum propagation of the 2048 x 2048 complex64 field
+(0/1 rectangles with random phase, 8 um pitch, 532 nm, z = 0.5 m), zero-padded to
+4096 x 4096, FP32: row FFT with padding, column FFT x H x IFFT, row IFFT with crop,
+through the C ABI (cwo_asm). The input is resident in HBM before timing starts.
+
+Prints one JSON line: throughput in planes/s over K timed steps (HIP events on the
+launch stream, bracketed by device synchronisation), the per-kernel durations
+measured live with HIP events inside the timed region, the roofline figure of the
+dominant kernel, the relative L2 error of the result against the FP64 oracle, and
+the oracle's own throughput on the host cores (a bounded sample: whole planes).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per launch of each kernel for an N x N field, M = 2N, complex64
+# intermediates: row_fwd reads the field and writes the N x M spectrum rows; col reads
+# and writes the N x M plane in place; row_inv reads it and writes the field.
+def stage_bytes(n: int) -> dict:
+    field = 8 * n * n
+    plane = 8 * n * (2 * n)
+    return {"row_fwd": field + plane, "col": 2 * plane, "row_inv": plane + field}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_1107_5578_amd/csrc/kernels.hip", "paper_1107_5578_amd/csrc/fft_device.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_asm2048.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(u_np, cfg, min_seconds: float = 10.0, max_planes: int = 30):
+    """The FP64 oracle on the host cores, on whole planes of the same workload."""
+    from oracle import _native, diffraction as D
+    threads = _native.max_threads()
+    t0 = time.perf_counter()
+    ref = None
+    done = 0
+    for _ in range(max_planes):
+        ref = D.asm(u_np, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+        done += 1
+        if time.perf_counter() - t0 > min_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return ref, {"value": done / dt, "unit": "planes/s", "cores": threads, "kind": "oracle",
+                 "sample": "%d whole 2048x2048 ASM plane(s) of the timed workload, FP64, "
+                           "%d OpenMP threads for the FFTs (%.1f s)" % (done, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(planes would shard across GPUs with no exchange; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1107_5578_amd import cwo, workloads as W
+
+    cfg = W.PLANE_2048
+    n = cfg.n
+    u_np = W.field_for(cfg)
+    dev = torch.device("cuda:0")
+    ctx = cwo.Context(0)
+    u = torch.from_numpy(u_np).to(dev)
+    out = torch.empty_like(u)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        ctx.asm(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    kernels = {}
+    for stage in (cwo.STAGE_ROW_FWD, cwo.STAGE_COL, cwo.STAGE_ROW_INV):
+        ms, cnt = ctx.profile_read(stage)
+        kernels[cwo.STAGE_NAMES[stage]] = {"avg_us": 1000.0 * ms / max(cnt, 1), "launches": cnt}
+    ctx.profile(False)
+
+    ms_per_step = total_ms / args.steps
+    value = 1000.0 / ms_per_step
+
+    sb = stage_bytes(n)
+    for name, rec in kernels.items():
+        rec["alg_bytes"] = sb[name]
+        rec["GBps"] = sb[name] / (rec["avg_us"] * 1e-6) / 1e9
+    dominant = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    d = kernels[dominant]
+    traffic = committed_traffic(dominant)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(d["GBps"], 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "plane_alg_bytes": sum(sb.values()),
+                "plane_GBps": round(sum(sb.values()) / (ms_per_step * 1e-3) / 1e9, 1)}
+
+    y = out.cpu().numpy()
+    line = {
+        "metric": "ASM planes/s at 2048^2 fp32 (plain per-call form)",
+        "value": round(value, 2),
+        "unit": "planes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "asm-2048: 2048x2048 complex64 rectangles+random phase, "
+                               "pitch 8um, 532nm, z=0.5m, padded to 4096x4096, plain cwo_asm",
+                   "n": n, "padded": 2 * n, "pitch_m": cfg.pitch, "wavelength_m": cfg.wavelength,
+                   "z_m": cfg.z, "seed": cfg.seed},
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        ref, base = cpu_baseline(u_np, cfg)
+        from oracle import diffraction as D
+        line["rel_l2_vs_oracle"] = float("%.3e" % D.rel_l2(y, ref))
+        line["cpu_baseline"] = base
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

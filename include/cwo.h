@@ -1,0 +1,130 @@
+/*
+ * cwo.h - C ABI of the MI355X diffraction library (libcwo.so).
+ *
+ * Scalar diffraction by FFT convolution, as defined in Shimobaba et al.,
+ * "Computational wave optics library for C++: CWO++ library" (arXiv 1107.5578):
+ *
+ *   angular spectrum method (Sec. 2.1.4, Eqs. ang1-ang3):
+ *       u2 = IFFT[ FFT[u1] * H_A ],  H_A(fx, fy) = exp(i z sqrt(k^2 - 4 pi^2 (fx^2 + fy^2))),
+ *       k = 2 pi / lambda, fx = p * dfx, dfx = 1/(Mx dx) (likewise y);
+ *       bins with lambda^2 (fx^2 + fy^2) > 1 are evanescent and get H_A = 0.
+ *   Fresnel diffraction, convolution form (Sec. 2.1.1, Eqs. fre_conv, fre_conv_fft,
+ *   fre_conv_prop_d):
+ *       u2 = C * IFFT[ FFT[u1] * FFT[h_F] ],  h_F(m, n) = exp(i pi/(lambda z) ((m dx)^2 + (n dy)^2)),
+ *       C = dx dy exp(i k z) / (i lambda z)  (the quadrature factor dx dy of Eq. fre_conv is kept).
+ *
+ * Both are convolution forms: the Ny x Nx field is zero-padded to My x Mx = 2Ny x 2Nx, the
+ * product spectrum is inverse transformed and the Ny x Nx result is cut out (Sec. 2.1.6),
+ * with the field at the top-left of the padded grid. The inverse transform carries
+ * 1/(Mx My). Output pitch equals input pitch (Sec. 2.1.1).
+ *
+ * Data layout: complex64 = interleaved float32 (re, im), row-major [ny][nx], x fastest
+ * (the paper's single-precision cwoComplex field). All field pointers are DEVICE pointers
+ * owned by the caller; the library never frees them. in == out is allowed.
+ *
+ * Ordering: cwo_asm / cwo_fresnel / cwo_zstack / cwo_gs are asynchronous and ordered on the
+ * given HIP stream (hipStream_t passed as void*, NULL = the null stream); they return
+ * after enqueueing. Calls on one context share its scratch memory: serialise them
+ * (one stream, or external synchronisation). cwo_submit / cwo_poll are thread-safe.
+ *
+ * Errors: every call returns a cwo_status. Parameters are validated before anything is
+ * launched. A device error makes the context return CWO_ERR_DEVICE from then on.
+ * NaN or Inf inside field data is not checked and propagates.
+ */
+#ifndef CWO_H
+#define CWO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CWO_OK = 0,
+    CWO_ERR_INVALID = -1,     /* null pointer, non-finite or non-positive pitch/wavelength,
+                                 non-finite z, Fresnel with z == 0, unknown kind/flag,
+                                 bad count */
+    CWO_ERR_UNSUPPORTED = -2, /* size not a power of two in [16, 4096], precision not built */
+    CWO_ERR_NOMEM = -3,       /* device allocation failed, or a job larger than the budget */
+    CWO_ERR_DEVICE = -4,      /* a HIP call failed; sticky on the context */
+    CWO_ERR_NOTFOUND = -5     /* unknown ticket */
+} cwo_status;
+
+/* Diffraction kinds (the paper's CWO_ANGULAR and CWO_FRESNEL_CONV selectors). */
+typedef enum { CWO_ANGULAR = 1, CWO_FRESNEL_CONV = 2 } cwo_kind;
+
+/* Storage precision of the padded intermediate planes; butterflies are always FP32 and
+ * the field in/out is always complex64. */
+typedef enum { CWO_PREC_F32 = 0, CWO_PREC_F16_STORAGE = 1, CWO_PREC_BF16_STORAGE = 2 } cwo_precision;
+
+/* Flags. CWO_FLAG_NOPAD keeps M = N (circular convolution without padding); it exists for
+ * exactness checks such as the plane-wave eigenfunction test, not for production use. */
+enum { CWO_FLAG_NOPAD = 1u };
+
+typedef struct {
+    int32_t nx, ny;      /* field size, each a power of two in [16, 4096]; x is the fastest axis */
+    double dx, dy;       /* sampling pitch [m], finite and > 0 (paper default 10e-6) */
+    double wavelength;   /* [m], finite and > 0 (paper default 633e-9) */
+    double z;            /* propagation distance [m], finite; z < 0 propagates back;
+                            z == 0 is the identity for ASM and CWO_ERR_INVALID for Fresnel */
+    int32_t kind;        /* cwo_kind; cwo_asm / cwo_fresnel also accept 0 */
+    int32_t precision;   /* cwo_precision */
+    uint32_t flags;      /* CWO_FLAG_* */
+} cwo_params;
+
+typedef struct cwo_ctx cwo_ctx; /* opaque */
+
+/* Create a context on HIP device `device`. hbm_budget_bytes bounds the scratch memory the
+ * context may hold at once (0 = no bound). Returns CWO_ERR_INVALID for a null ctx pointer
+ * or a bad device ordinal, CWO_ERR_DEVICE if the device cannot be used. */
+cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes);
+
+/* Wait for all work the context launched, then free its scratch, tables and caches.
+ * A null ctx is CWO_ERR_INVALID. */
+cwo_status cwo_destroy(cwo_ctx* ctx);
+
+/* Angular spectrum propagation of one field (Sec. 2.1.4, Eq. ang3, padded per Sec. 2.1.6).
+ * in, out: device complex64 [ny][nx]. Scratch: ny * 2nx complex64 held by the context. */
+cwo_status cwo_asm(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out, void* hip_stream);
+
+/* Fresnel diffraction, convolution form (Sec. 2.1.1, Eq. fre_conv_fft), same layout as
+ * cwo_asm. The two 1-D factors of FFT[h_F] are cached per parameter set. */
+cwo_status cwo_fresnel(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
+                       void* hip_stream);
+
+/* Validate a parameter set for `kind` without touching any device: the same checks the
+ * propagation calls run first. Returns CWO_OK, CWO_ERR_INVALID or CWO_ERR_UNSUPPORTED. */
+cwo_status cwo_check_params(const cwo_params* p, int32_t kind);
+
+/* Bytes of scratch one propagation of this parameter set needs (0 if the set is invalid). */
+size_t cwo_scratch_bytes(const cwo_params* p);
+
+/* Kernel stages, for per-kernel timing. */
+typedef enum {
+    CWO_STAGE_ROW_FWD = 0,   /* zero-pad + forward row FFT */
+    CWO_STAGE_COL = 1,       /* column FFT, transfer function, inverse column FFT, crop */
+    CWO_STAGE_ROW_INV = 2,   /* inverse row FFT + crop + 1/(Mx My) */
+    CWO_STAGE_TABLES = 3,    /* twiddle and Fresnel transfer-vector generation */
+    CWO_STAGE_COUNT = 8
+} cwo_stage;
+
+/* Per-kernel timing for benchmarks. enable != 0 clears the totals and brackets every
+ * kernel the context launches afterwards with HIP events on the launch stream; 0 stops.
+ * cwo_profile_read waits for the recorded events and returns the summed milliseconds and
+ * the number of launches of one stage. */
+cwo_status cwo_profile(cwo_ctx* ctx, int32_t enable);
+cwo_status cwo_profile_read(cwo_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* cwo_strerror(cwo_status s);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t cwo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CWO_H */

@@ -24,8 +24,8 @@ Readings of points the paper leaves open (each one is listed in the design doc):
 * The field sits at the top-left of the padded grid and the result is cropped
   from the top-left (a circular shift commutes with the circular convolution,
   so any consistent placement gives the same crop).
-* The frequency pitch is 1/(M*d) of the padded grid; bin p maps to p/(M*d) for
-  p < M/2 and to (p - M)/(M*d) otherwise.
+* The frequency pitch is df = 1/(M*d) of the padded grid; bin p maps to p*df for
+  p < M/2 and to (p - M)*df otherwise.
 * The inverse transform carries the 1/(Mx*My) normalisation.
 * The ASM radicand is written k^2 * (1 - lambda^2*(fx^2 + fy^2)); the bin is
   propagating when s = (lambda*fx)^2 + (lambda*fy)^2 <= 1 (s == 1 counts as
@@ -72,10 +72,12 @@ def pad(u1: np.ndarray, my: int, mx: int) -> np.ndarray:
 # ---- step 3: frequencies of the padded grid ----------------------------------
 
 def frequencies(m: int, d: float) -> np.ndarray:
-    """Spatial frequency of each DFT bin: p/(M*d) for p < M/2, else (p - M)/(M*d)."""
+    """Spatial frequency of each DFT bin as index times pitch (Sec. 2.1.4: f = m1 * df):
+    df = 1/(M*d) and the signed index is p for p < M/2, else p - M."""
     p = np.arange(m, dtype=np.float64)
     signed = np.where(p < m / 2, p, p - m)
-    return signed / (m * d)
+    df = 1.0 / (m * d)
+    return signed * df
 
 
 # ---- step 4a: angular-spectrum transfer function (Eq. ang2) -------------------

@@ -1,0 +1,238 @@
+// Device-side FFT building blocks for gfx950 (wave64, LDS-staged Stockham).
+//
+// A length-M transform is done by one group of T = M/E threads; each thread
+// holds E complex values in registers. Before every pass thread j holds the
+// elements j + r*T (r < E) of the current sequence; a radix-RP pass performs
+// E/RP butterflies b = j + i*T, each reading inputs b + kk*(M/RP), multiplying
+// by the Stockham twiddle W_{Ns*RP}^{(b mod Ns)*kk} and writing outputs to
+// (b / Ns)*Ns*RP + (b mod Ns) + kk*Ns, where Ns is the product of the radices
+// of the earlier passes. Intermediate passes exchange through LDS; the first
+// pass reads registers loaded straight from global memory and the last pass
+// leaves the result in registers in natural order (element j + r*T), so global
+// loads and stores are both unit-stride across a wavefront.
+//
+// Sign convention: forward uses exp(-2*pi*i*jk/M), inverse exp(+2*pi*i*jk/M),
+// both unnormalised (the DFT pair the paper's FFT/IFFT primitives compute).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cwo {
+
+constexpr int FWD = -1;
+constexpr int INV = +1;
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(__fmaf_rn(a.x, b.x, -a.y * b.y), __fmaf_rn(a.x, b.y, a.y * b.x));
+}
+// multiply by w (DIR = FWD) or conj(w) (DIR = INV); tables store exp(-2*pi*i*k/M)
+template <int DIR>
+__device__ __forceinline__ float2 ctw(float2 a, float2 w) {
+    if constexpr (DIR == FWD) return cmul(a, w);
+    else return make_float2(__fmaf_rn(a.x, w.x, a.y * w.y), __fmaf_rn(a.y, w.x, -a.x * w.y));
+}
+// multiply by exp(DIR * i*pi/2): -i forward, +i inverse
+template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+    if constexpr (DIR == FWD) return make_float2(a.y, -a.x);
+    else return make_float2(-a.y, a.x);
+}
+
+// Multiply by exp(DIR * 2*pi*i*m/R) for a compile-time m, cheap forms for multiples of pi/4.
+template <int R, int M_, int DIR>
+__device__ __forceinline__ float2 wconst(float2 a) {
+    constexpr int m = ((M_ % R) + R) % R;
+    if constexpr (m == 0) return a;
+    else if constexpr (8 * m % R == 0) {
+        constexpr int oct = 8 * m / R;  // angle = oct * pi/4
+        constexpr float h = 0.70710678118654752440f;
+        if constexpr (oct == 2) return rot90<DIR>(a);
+        else if constexpr (oct == 4) return make_float2(-a.x, -a.y);
+        else if constexpr (oct == 6) return rot90<-DIR>(a);
+        else {
+            // (+-1 +- i)/sqrt(2): angle = DIR*oct*pi/4
+            constexpr float c = (oct == 1 || oct == 7) ? h : -h;
+            constexpr float s0 = (oct == 1 || oct == 3) ? h : -h;  // sin(oct*pi/4)
+            constexpr float s = (DIR == FWD) ? -s0 : s0;
+            return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+        }
+    } else {
+        // general angle 2*pi*m/R with R <= 32: cos/sin of multiples of pi/16
+        constexpr double PI = 3.14159265358979323846;
+        // constexpr evaluation through a small table of cos(k*pi/16), k = 0..8
+        constexpr double ctab[9] = {1.0, 0.98078528040323044913, 0.92387953251128675613,
+                                    0.83146961230254523708, 0.70710678118654752440,
+                                    0.55557023301960222474, 0.38268343236508977173,
+                                    0.19509032201612826785, 0.0};
+        constexpr int k32 = m * (32 / R);  // angle in units of pi/16, 0..31
+        constexpr int q = k32 / 8, rr = k32 % 8;
+        // cos and sin of (q*pi/2 + rr*pi/16)
+        constexpr double c0 = ctab[rr], s0 = ctab[8 - rr];
+        constexpr double cc = q == 0 ? c0 : q == 1 ? -s0 : q == 2 ? -c0 : s0;
+        constexpr double ss = q == 0 ? s0 : q == 1 ? c0 : q == 2 ? -s0 : -c0;
+        constexpr float c = (float)cc;
+        constexpr float s = (float)(DIR == FWD ? -ss : ss);
+        (void)PI;
+        return make_float2(__fmaf_rn(c, a.x, -s * a.y), __fmaf_rn(c, a.y, s * a.x));
+    }
+}
+
+// ---- small DFTs on register arrays, in place, natural output order ------------
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    float2 t2 = cadd(a1, a3), t3 = rot90<DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// DFT of R points held in v[OFF + STRIDE*k], k < R, result in the same slots in natural order.
+template <int R, int DIR, int OFF = 0, int STRIDE = 1, int N>
+__device__ __forceinline__ void dft(float2 (&v)[N]) {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "radix");
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        dft2<DIR>(v[OFF], v[OFF + STRIDE]);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(v[OFF], v[OFF + STRIDE], v[OFF + 2 * STRIDE], v[OFF + 3 * STRIDE]);
+    } else if constexpr (R == 8 || R == 32) {
+        // radix-2 decimation in time over two half-size DFTs
+        constexpr int H = R / 2;
+        dft<H, DIR, OFF, 2 * STRIDE>(v);           // even samples
+        dft<H, DIR, OFF + STRIDE, 2 * STRIDE>(v);  // odd samples
+        float2 t[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k] = v[OFF + k * STRIDE];
+        // t[2k] = E[k], t[2k+1] = O[k]
+        float2 o[R];
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((o[K] = cadd(t[2 * K], wconst<R, K, DIR>(t[2 * K + 1])),
+              o[K + H] = csub(t[2 * K], wconst<R, K, DIR>(t[2 * K + 1]))), ...);
+        }(std::make_integer_sequence<int, H>{});
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[OFF + k * STRIDE] = o[k];
+    } else {  // R == 16: 4 x 4
+        // stage 1: for each n2, DFT4 over n1 of x[4*n1 + n2]; result Y[n2][k1] kept at slot 4*k1 + n2
+        dft4<DIR>(v[OFF + 0 * STRIDE], v[OFF + 4 * STRIDE], v[OFF + 8 * STRIDE], v[OFF + 12 * STRIDE]);
+        dft4<DIR>(v[OFF + 1 * STRIDE], v[OFF + 5 * STRIDE], v[OFF + 9 * STRIDE], v[OFF + 13 * STRIDE]);
+        dft4<DIR>(v[OFF + 2 * STRIDE], v[OFF + 6 * STRIDE], v[OFF + 10 * STRIDE], v[OFF + 14 * STRIDE]);
+        dft4<DIR>(v[OFF + 3 * STRIDE], v[OFF + 7 * STRIDE], v[OFF + 11 * STRIDE], v[OFF + 15 * STRIDE]);
+        // twiddles W16^(n2*k1) on slot 4*k1 + n2
+        float2 y[16];
+        [&]<int... S>(std::integer_sequence<int, S...>) {
+            ((y[S] = wconst<16, (S % 4) * (S / 4), DIR>(v[OFF + S * STRIDE])), ...);
+        }(std::make_integer_sequence<int, 16>{});
+        // stage 2: for each k1, DFT4 over n2 of Y[n2][k1] -> X[k1 + 4*k2]
+        dft4<DIR>(y[0], y[1], y[2], y[3]);
+        dft4<DIR>(y[4], y[5], y[6], y[7]);
+        dft4<DIR>(y[8], y[9], y[10], y[11]);
+        dft4<DIR>(y[12], y[13], y[14], y[15]);
+        // y[4*k1 + k2] = X[k1 + 4*k2]
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[OFF + (k1 + 4 * k2) * STRIDE] = y[4 * k1 + k2];
+    }
+}
+
+// ---- pass plans -------------------------------------------------------------
+
+// Radix of pass p for a length-M transform with E values per thread: the first
+// pass takes the remainder M / E^(P-1), the others take E (E itself may be 32,
+// then later passes use 16 and each thread runs two butterflies).
+template <int M, int E>
+struct Plan {
+    static constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+    static constexpr int LM = log2i(M);
+    static constexpr int LR = (E == 32) ? 4 : log2i(E);  // bits per full pass
+    static constexpr int LE = log2i(E);
+    // E == 32: first pass radix 32 (if it fits), the rest radix 16
+    static constexpr int FIRST_BITS =
+        (E == 32) ? LE : ((LM % LR) == 0 ? LR : (LM % LR));
+    static constexpr int REST = (LM - FIRST_BITS) / LR;
+    static constexpr int PASSES = 1 + REST;
+    static constexpr int T = M / E;
+    static_assert((E == 32 ? (LM - LE) % 4 == 0 : true), "E=32 plans need M = 32 * 16^k");
+    static constexpr int radix(int p) { return p == 0 ? (1 << FIRST_BITS) : (1 << LR); }
+    static constexpr int ns(int p) { return p == 0 ? 1 : (1 << FIRST_BITS) << (LR * (p - 1)); }
+};
+
+// LDS slot of element e: one pad slot every 16 elements keeps the strided
+// Stockham writes spread over the banks
+__device__ __forceinline__ int lds_slot(int e) { return e + (e >> 4); }
+template <int M>
+constexpr int lds_elems() { return M + M / 16; }
+
+// One Stockham pass. Writes results to LDS (intermediate pass) or back into
+// registers in natural order (last pass).
+template <int M, int E, int RP, int NS, bool LAST, int DIR>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j,
+                                              const float2* __restrict__ tw) {
+    constexpr int T = M / E;
+    constexpr int NB = E / RP;  // butterflies per thread
+    float2 out[E];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = j + i * T;
+        const int k = b & (NS - 1);
+        float2 u[RP];
+#pragma unroll
+        for (int kk = 0; kk < RP; ++kk) u[kk] = v[i + kk * NB];
+        if constexpr (NS > 1) {
+            constexpr int STEP = M / (NS * RP);
+#pragma unroll
+            for (int kk = 1; kk < RP; ++kk) u[kk] = ctw<DIR>(u[kk], tw[k * kk * STEP]);
+        }
+        dft<RP, DIR>(u);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int kk = 0; kk < RP; ++kk) out[i + kk * NB] = u[kk];
+        } else {
+            const int base = (b / NS) * NS * RP + k;
+#pragma unroll
+            for (int kk = 0; kk < RP; ++kk) lds[lds_slot(base + kk * NS)] = u[kk];
+        }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = out[r];
+    }
+}
+
+// Full transform. On entry v[r] = x[j + r*T]; on exit v[r] = X[j + r*T].
+// All threads of the block must call it (it contains block barriers).
+template <int M, int E, int DIR>
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+    using P = Plan<M, E>;
+    constexpr int T = P::T;
+    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+        (([&] {
+             constexpr int p = Ps;
+             constexpr int RP = P::radix(p);
+             constexpr int NS = P::ns(p);
+             constexpr bool LAST = (p == P::PASSES - 1);
+             stockham_pass<M, E, RP, NS, LAST, DIR>(v, lds, j, tw);
+             if constexpr (!LAST) {
+                 __syncthreads();
+#pragma unroll
+                 for (int r = 0; r < E; ++r) v[r] = lds[lds_slot(j + r * T)];
+                 __syncthreads();
+             }
+         }()),
+         ...);
+    }(std::make_integer_sequence<int, P::PASSES>{});
+}
+
+}  // namespace cwo

@@ -1,0 +1,238 @@
+"""Python binding of libcwo (argument marshalling only).
+
+Every step of a propagation runs in the HIP kernels of ``libcwo.so``; this
+module only converts arguments, allocates output tensors with PyTorch and
+passes device pointers and the current HIP stream through the C ABI declared in
+``include/cwo.h``. Importing it raises if the library has not been built.
+
+Fields are ``torch.complex64`` tensors on a ROCm device, contiguous, shape
+``[ny, nx]`` (x fastest), as the C ABI requires.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcwo.so")
+
+CWO_OK = 0
+CWO_ERR_INVALID = -1
+CWO_ERR_UNSUPPORTED = -2
+CWO_ERR_NOMEM = -3
+CWO_ERR_DEVICE = -4
+CWO_ERR_NOTFOUND = -5
+
+ANGULAR = 1
+FRESNEL_CONV = 2
+
+PREC_F32 = 0
+PREC_F16 = 1
+PREC_BF16 = 2
+_PRECISIONS = {"f32": PREC_F32, "fp32": PREC_F32, "f16": PREC_F16, "fp16": PREC_F16,
+               "bf16": PREC_BF16}
+
+FLAG_NOPAD = 1
+
+STAGE_ROW_FWD = 0
+STAGE_COL = 1
+STAGE_ROW_INV = 2
+STAGE_TABLES = 3
+STAGE_NAMES = {STAGE_ROW_FWD: "row_fwd", STAGE_COL: "col", STAGE_ROW_INV: "row_inv",
+               STAGE_TABLES: "tables"}
+
+
+class CwoError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = strerror(status)
+        super().__init__("%s: %s (status %d)" % (what, msg, status) if what else msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("wavelength", ctypes.c_double), ("z", ctypes.c_double),
+        ("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+# name -> (restype, argtypes) for every symbol include/cwo.h declares
+SIGNATURES = {
+    "cwo_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t]),
+    "cwo_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "cwo_asm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_fresnel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_check_params": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.c_int32]),
+    "cwo_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
+    "cwo_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "cwo_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "cwo_strerror": (ctypes.c_char_p, [ctypes.c_int32]),
+    "cwo_version": (ctypes.c_int32, []),
+}
+
+
+def load():
+    """Load libcwo.so (raises FileNotFoundError when it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise FileNotFoundError(
+                    "libcwo.so is not built (run `python -m paper_1107_5578_amd.build`)")
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load().cwo_strerror(int(status)).decode()
+
+
+def make_params(nx, ny, dx, dy=None, wavelength=633e-9, z=0.1, kind=0, precision="f32",
+                nopad=False) -> Params:
+    prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Params(int(nx), int(ny), float(dx), float(dx if dy is None else dy),
+                  float(wavelength), float(z), int(kind), prec,
+                  FLAG_NOPAD if nopad else 0)
+
+
+def check_params(p: Params, kind: int) -> int:
+    return int(load().cwo_check_params(ctypes.byref(p), int(kind)))
+
+
+class Context:
+    """A libcwo context on one device: scratch, twiddle tables and caches."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        st = self._lib.cwo_create(ctypes.byref(h), int(device), int(hbm_budget_bytes))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_create")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            st = self._lib.cwo_destroy(self.handle)
+            self.handle = None
+            if st != CWO_OK:
+                raise CwoError(st, "cwo_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool):
+        """Start (clearing totals) or stop per-kernel HIP-event timing."""
+        st = self._lib.cwo_profile(self.handle, 1 if enable else 0)
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_profile")
+
+    def profile_read(self, stage: int):
+        """(total milliseconds, launches) of one kernel stage since profiling started."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        st = self._lib.cwo_profile_read(self.handle, int(stage), ctypes.byref(ms), ctypes.byref(n))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_profile_read")
+        return ms.value, n.value
+
+    # -- helpers ------------------------------------------------------------
+    @staticmethod
+    def _field(u):
+        import torch
+        if not isinstance(u, torch.Tensor) or u.dtype != torch.complex64 or u.dim() != 2:
+            raise TypeError("field must be a 2-D torch.complex64 tensor")
+        if u.device.type != "cuda":
+            raise TypeError("field must live on a ROCm device")
+        if not u.is_contiguous():
+            raise ValueError("field must be contiguous [ny, nx]")
+        return u
+
+    @staticmethod
+    def _stream(u, stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(u.device)
+        return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+    def _propagate(self, fn, kind, u, dx, dy, wavelength, z, precision, nopad, out, stream):
+        import torch
+        u = self._field(u)
+        ny, nx = u.shape
+        p = make_params(nx, ny, dx, dy, wavelength, z, kind, precision, nopad)
+        if out is None:
+            out = torch.empty_like(u)
+        else:
+            out = self._field(out)
+            if out.shape != u.shape or out.device != u.device:
+                raise ValueError("out must match the field's shape and device")
+        st = fn(self.handle, ctypes.byref(p), ctypes.c_void_p(u.data_ptr()),
+                ctypes.c_void_p(out.data_ptr()), self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, fn.__name__)
+        return out
+
+    def asm(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
+            nopad=False, out=None, stream=None):
+        """Angular spectrum propagation by z (stream-ordered; returns the output tensor)."""
+        return self._propagate(self._lib.cwo_asm, ANGULAR, u, dx, dy, wavelength, z, precision,
+                               nopad, out, stream)
+
+    def fresnel(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
+                nopad=False, out=None, stream=None):
+        """Fresnel diffraction (convolution form) by z."""
+        return self._propagate(self._lib.cwo_fresnel, FRESNEL_CONV, u, dx, dy, wavelength, z,
+                               precision, nopad, out, stream)
+
+
+_default = {}
+
+
+def context(device: int = 0) -> Context:
+    """The process-wide default context of a device."""
+    c = _default.get(device)
+    if c is None:
+        c = Context(device)
+        _default[device] = c
+    return c
+
+
+def asm(u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, **kw):
+    return context(u.device.index or 0).asm(u, dx, dy, wavelength, z, **kw)
+
+
+def fresnel(u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, **kw):
+    return context(u.device.index or 0).fresnel(u, dx, dy, wavelength, z, **kw)
+
+
+def algorithmic_bytes(nx: int, ny: int, intermediate_bytes: int = 8) -> int:
+    """Bytes one padded propagation must move: read the field, write and re-read the
+    Ny x 2Nx spectrum plane twice (row pass, column pass), write the field."""
+    mx = 2 * nx
+    field = 8 * nx * ny
+    plane = intermediate_bytes * ny * mx
+    return field + plane + 2 * plane + plane + field  # row, column (r+w), row-inverse (r)
+
+
+__all__ = ["Context", "CwoError", "Params", "make_params", "check_params", "context", "asm",
+           "fresnel", "load", "strerror", "algorithmic_bytes", "math"]

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Gate per plane: relative L2 error <= 1e-5 for FP32 (the bound the method's
+production target sets). Element by element, |y - y_ref| <= 1e-5 * max|y_ref|:
+an FP32 Stockham transform of length M carries a relative error of about
+eps32 * log2(M) ~ 1e-6 per output, and each propagation chains four such
+transforms plus the transfer-function rounding (phase error <= 2^-24 revolution),
+so 1e-5 of the plane's peak leaves a margin of several times over the expected
+worst case. Inputs are seeded and identical bytes go to both sides.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+ELEM = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1107_5578_amd import cwo
+    c = cwo.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(ctx, kind, u, dx, dy, lam, z, nopad=False):
+    import torch
+    note("%s n=%s dx=%g dy=%g lam=%g z=%g nopad=%s" % (kind, u.shape, dx, dy, lam, z, nopad))
+    t = torch.from_numpy(np.ascontiguousarray(u.astype(np.complex64))).to("cuda")
+    fn = ctx.asm if kind == D.ASM else ctx.fresnel
+    out = fn(t, dx, dy, lam, z, nopad=nopad)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check(y, ref, rel_tol=REL_L2, elem_tol=ELEM, label=""):
+    rl = D.rel_l2(y, ref)
+    peak = float(np.max(np.abs(ref)))
+    emax = float(np.max(np.abs(y.astype(np.complex128) - ref)))
+    note("%s rel_l2=%.3e max_abs_err/peak=%.3e" % (label, rl, emax / peak if peak else emax))
+    assert np.all(np.isfinite(y))
+    assert rl <= rel_tol, (label, rl)
+    assert emax <= elem_tol * peak, (label, emax / peak)
+    return rl
+
+
+def test_plain_asm_256(ctx):
+    cfg = W.PLAIN_ASM_256
+    u = W.field_for(cfg)
+    y = gpu_run(ctx, D.ASM, u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+    ref = D.asm(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+    check(y, ref, label="asm-256")
+
+
+SIZES = [(16, 16), (32, 16), (16, 64), (64, 64), (128, 32), (256, 512), (512, 256),
+         (1024, 1024), (4096, 16), (16, 2048)]
+
+
+@pytest.mark.parametrize("kind", [D.ASM, D.FRESNEL])
+@pytest.mark.parametrize("nx,ny", SIZES)
+def test_sizes(ctx, kind, nx, ny):
+    u = W.uniform_random_field(nx, seed=nx * 7 + ny, ny=ny)
+    dx, dy, lam, z = 8e-6, 6e-6, 532e-9, (0.05 if (nx + ny) % 3 else -0.12)
+    y = gpu_run(ctx, kind, u, dx, dy, lam, z)
+    ref = D.propagate(u, kind, dx, dy, lam, z)
+    check(y, ref, label="%s-%dx%d" % (kind, nx, ny))
+
+
+@pytest.mark.parametrize("p0,q0", [(0, 0), (3, -5), (17, 9)])
+def test_plane_wave_nopad(ctx, p0, q0):
+    # closed form, independent of the oracle: the plane wave picks up exp(i z kappa)
+    n, dx, dy, lam, z = 64, 10e-6, 8e-6, 633e-9, 0.137
+    jy, jx = np.mgrid[0:n, 0:n]
+    u = np.exp(2j * np.pi * (p0 * jx / n + q0 * jy / n))
+    y = gpu_run(ctx, D.ASM, u, dx, dy, lam, z, nopad=True)
+    k = 2 * np.pi / lam
+    fx, fy = p0 / (n * dx), q0 / (n * dy)
+    kappa = math.sqrt(k * k - 4 * np.pi ** 2 * (fx * fx + fy * fy))
+    check(y, u.astype(np.complex64).astype(np.complex128) * np.exp(1j * z * kappa),
+          label="plane-wave")
+
+
+def test_asm_z0_identity(ctx):
+    u = W.uniform_random_field(128, 5, ny=64)
+    y = gpu_run(ctx, D.ASM, u, 10e-6, 10e-6, 633e-9, 0.0)
+    check(y, u.astype(np.complex128), label="z0")
+
+
+def test_round_trip_nopad(ctx):
+    import torch
+    u = W.uniform_random_field(256, 9)
+    t = torch.from_numpy(u).to("cuda")
+    f = ctx.asm(t, 8e-6, 8e-6, 532e-9, 0.3, nopad=True)
+    b = ctx.asm(f, 8e-6, 8e-6, 532e-9, -0.3, nopad=True)
+    torch.cuda.synchronize()
+    check(b.cpu().numpy(), u.astype(np.complex128), label="round-trip")
+
+
+def test_evanescent_cut(ctx):
+    # 0.3 um pitch at 633 nm: a large part of the spectrum is evanescent
+    u = W.uniform_random_field(64, 11)
+    y = gpu_run(ctx, D.ASM, u, 0.3e-6, 0.3e-6, 633e-9, 2e-6)
+    ref = D.asm(u, 0.3e-6, 0.3e-6, 633e-9, 2e-6)
+    check(y, ref, label="evanescent")
+
+
+def test_evanescent_exact_boundary(ctx):
+    # dx = 2^-20, lambda = 2^-18, M = N = 16: bin 4 has s == 1 exactly (propagating,
+    # H = 1), bin 5 is evanescent (H = 0); both sides take the decision in FP64
+    n, dx, lam = 16, 2.0 ** -20, 2.0 ** -18
+    jx = np.arange(n)[None, :].repeat(n, 0)
+    u = np.exp(2j * np.pi * 4 * jx / n) + 0.5 * np.exp(2j * np.pi * 5 * jx / n)
+    y = gpu_run(ctx, D.ASM, u, dx, dx, lam, 0.37, nopad=True)
+    expect = np.exp(2j * np.pi * 4 * jx / n)
+    check(y, expect, label="boundary")
+    check(y, D.asm(u.astype(np.complex64), dx, dx, lam, 0.37, nopad=True), label="boundary-oracle")
+
+
+def test_in_place(ctx):
+    import torch
+    u = W.uniform_random_field(256, 13)
+    t = torch.from_numpy(u).to("cuda")
+    ctx.asm(t, 10e-6, 10e-6, 633e-9, 0.1, out=t)
+    torch.cuda.synchronize()
+    check(t.cpu().numpy(), D.asm(u, 10e-6, 10e-6, 633e-9, 0.1), label="in-place")
+
+
+def test_deterministic(ctx):
+    import torch
+    u = torch.from_numpy(W.uniform_random_field(512, 17)).to("cuda")
+    a = ctx.asm(u, 10e-6, 10e-6, 633e-9, 0.1)
+    b = ctx.asm(u, 10e-6, 10e-6, 633e-9, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_linearity(ctx):
+    import torch
+    u = W.uniform_random_field(256, 21)
+    v = W.uniform_random_field(256, 22)
+    al, be = np.complex64(0.3 - 1.2j), np.complex64(-2.0 + 0.5j)
+    w = (al * u + be * v).astype(np.complex64)
+    tu, tv, tw = (torch.from_numpy(a).to("cuda") for a in (u, v, w))
+    pu = ctx.fresnel(tu, 8e-6, 8e-6, 532e-9, 0.05)
+    pv = ctx.fresnel(tv, 8e-6, 8e-6, 532e-9, 0.05)
+    pw = ctx.fresnel(tw, 8e-6, 8e-6, 532e-9, 0.05)
+    torch.cuda.synchronize()
+    lhs = pw.cpu().numpy().astype(np.complex128)
+    rhs = al * pu.cpu().numpy().astype(np.complex128) + be * pv.cpu().numpy().astype(np.complex128)
+    assert D.rel_l2(lhs, rhs) < 1e-6
+
+
+@pytest.mark.parametrize("kind", [D.ASM, D.FRESNEL])
+def test_plane_2048(ctx, kind):
+    cfg = W.PLANE_2048
+    u = W.field_for(cfg)
+    y = gpu_run(ctx, kind, u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+    ref = D.propagate(u, kind, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+    check(y, ref, label="%s-2048" % kind)
+
+
+def test_max_size_4096(ctx):
+    u = W.rectangles_field(4096, 4)
+    y = gpu_run(ctx, D.ASM, u, 8e-6, 8e-6, 473e-9, 0.8)
+    ref = D.asm(u, 8e-6, 8e-6, 473e-9, 0.8)
+    check(y, ref, label="asm-4096")
+
+
+def test_invalid_calls_raise(ctx):
+    import torch
+    from paper_1107_5578_amd import cwo
+    u = torch.zeros((64, 48), dtype=torch.complex64, device="cuda")
+    with pytest.raises(cwo.CwoError) as e:
+        ctx.asm(u, 10e-6)
+    assert e.value.status == cwo.CWO_ERR_UNSUPPORTED
+    u = torch.zeros((64, 64), dtype=torch.complex64, device="cuda")
+    with pytest.raises(cwo.CwoError) as e:
+        ctx.fresnel(u, 10e-6, z=0.0)
+    assert e.value.status == cwo.CWO_ERR_INVALID
