@@ -57,7 +57,7 @@ def committed_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(u_np, cfg, min_seconds: float = 10.0, max_planes: int = 30):
+def cpu_baseline(u_np, cfg, kind="asm", min_seconds: float = 10.0, max_planes: int = 30):
     """The FP64 oracle on the host cores, on whole planes of the same workload."""
     from oracle import _native, diffraction as D
     threads = _native.max_threads()
@@ -65,14 +65,15 @@ def cpu_baseline(u_np, cfg, min_seconds: float = 10.0, max_planes: int = 30):
     ref = None
     done = 0
     for _ in range(max_planes):
-        ref = D.asm(u_np, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+        ref = D.propagate(u_np, kind, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
         done += 1
         if time.perf_counter() - t0 > min_seconds:
             break
     dt = time.perf_counter() - t0
     return ref, {"value": done / dt, "unit": "planes/s", "cores": threads, "kind": "oracle",
-                 "sample": "%d whole 2048x2048 ASM plane(s) of the timed workload, FP64, "
-                           "%d OpenMP threads for the FFTs (%.1f s)" % (done, threads, dt)}
+                 "sample": "%d whole %dx%d %s plane(s) of the timed workload, FP64, "
+                           "%d OpenMP threads for the FFTs (%.1f s)"
+                           % (done, u_np.shape[1], u_np.shape[0], kind, threads, dt)}
 
 
 def main():
@@ -81,6 +82,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kind", choices=["asm", "fresnel"], default="asm",
+                    help="transfer function of the timed plane (the headline metric is asm)")
+    ap.add_argument("--n", type=int, default=0,
+                    help="field size other than the headline 2048 (a side measurement)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size three times (a plain copy "
+                         "kernel of known traffic, to calibrate profiler byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -95,16 +103,18 @@ def main():
     from paper_1107_5578_amd import cwo, workloads as W
 
     cfg = W.PLANE_2048
-    n = cfg.n
-    u_np = W.field_for(cfg)
+    n = args.n or cfg.n
+    u_np = W.field_for(cfg, n)
     dev = torch.device("cuda:0")
     ctx = cwo.Context(0)
     u = torch.from_numpy(u_np).to(dev)
     out = torch.empty_like(u)
     stream = torch.cuda.current_stream(dev)
 
+    prop = ctx.asm if args.kind == "asm" else ctx.fresnel
+
     def step():
-        ctx.asm(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=out)
+        prop(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=out)
 
     for _ in range(args.warmup):
         step()
@@ -144,7 +154,7 @@ def main():
 
     y = out.cpu().numpy()
     line = {
-        "metric": "ASM planes/s at 2048^2 fp32 (plain per-call form)",
+        "metric": "%s planes/s at %d^2 fp32 (plain per-call form)" % (args.kind.upper(), n),
         "value": round(value, 2),
         "unit": "planes/s",
         "n_gpus": 1,
@@ -156,8 +166,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "asm-2048: 2048x2048 complex64 rectangles+random phase, "
-                               "pitch 8um, 532nm, z=0.5m, padded to 4096x4096, plain cwo_asm",
+        "config": {"workload": "%s-%d: %dx%d complex64 rectangles+random phase, pitch 8um, "
+                               "532nm, z=0.5m, padded to %dx%d, plain per-call form"
+                               % (args.kind, n, n, n, 2 * n, 2 * n),
                    "n": n, "padded": 2 * n, "pitch_m": cfg.pitch, "wavelength_m": cfg.wavelength,
                    "z_m": cfg.z, "seed": cfg.seed},
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
@@ -165,11 +176,19 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        ref, base = cpu_baseline(u_np, cfg)
+        ref, base = cpu_baseline(u_np, cfg, args.kind)
         from oracle import diffraction as D
         line["rel_l2_vs_oracle"] = float("%.3e" % D.rel_l2(y, ref))
         line["cpu_baseline"] = base
     print(json.dumps(line), flush=True)
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
     ctx.close()
 
 

@@ -175,64 +175,118 @@ __device__ __forceinline__ int lds_slot(int e) { return e + (e >> 4); }
 template <int M>
 constexpr int lds_elems() { return M + M / 16; }
 
-// One Stockham pass. Writes results to LDS (intermediate pass) or back into
-// registers in natural order (last pass).
-template <int M, int E, int RP, int NS, bool LAST, int DIR>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j,
+// Block barrier for the LDS exchanges only. Threads of a block communicate through
+// LDS alone (every global location is written by exactly one thread), so the
+// barrier waits for this thread's LDS operations but leaves global loads and
+// stores in flight; prefetched loads and the previous item's stores overlap the
+// transform.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// P interleaved transforms share each LDS slot (P complex values, 8*P bytes), so
+// one thread moves all of them with a single 8- or 16-byte LDS access.
+template <int P>
+__device__ __forceinline__ void lds_put(float2* lds, int slot, const float2 (&x)[P]) {
+    if constexpr (P == 1) {
+        lds[slot] = x[0];
+    } else {
+        static_assert(P == 2, "P");
+        reinterpret_cast<float4*>(lds)[slot] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+    }
+}
+template <int P>
+__device__ __forceinline__ void lds_get(const float2* lds, int slot, float2 (&x)[P]) {
+    if constexpr (P == 1) {
+        x[0] = lds[slot];
+    } else {
+        const float4 t = reinterpret_cast<const float4*>(lds)[slot];
+        x[0] = make_float2(t.x, t.y);
+        x[1] = make_float2(t.z, t.w);
+    }
+}
+
+// One Stockham pass over P transforms that share twiddles. Writes results to LDS
+// (intermediate pass) or back into registers in natural order (last pass).
+template <int M, int E, int P, int RP, int NS, bool LAST, int DIR>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, int j,
                                               const float2* __restrict__ tw) {
     constexpr int T = M / E;
-    constexpr int NB = E / RP;  // butterflies per thread
-    float2 out[E];
+    constexpr int NB = E / RP;  // butterflies per thread and transform
+    float2 out[P][E];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int b = j + i * T;
         const int k = b & (NS - 1);
-        float2 u[RP];
-#pragma unroll
-        for (int kk = 0; kk < RP; ++kk) u[kk] = v[i + kk * NB];
+        float2 w[RP];
         if constexpr (NS > 1) {
             constexpr int STEP = M / (NS * RP);
 #pragma unroll
-            for (int kk = 1; kk < RP; ++kk) u[kk] = ctw<DIR>(u[kk], tw[k * kk * STEP]);
+            for (int kk = 1; kk < RP; ++kk) w[kk] = tw[k * kk * STEP];
         }
-        dft<RP, DIR>(u);
+        float2 u[P][RP];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int kk = 0; kk < RP; ++kk) u[p][kk] = v[p][i + kk * NB];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int kk = 1; kk < RP; ++kk) u[p][kk] = ctw<DIR>(u[p][kk], w[kk]);
+            }
+            dft<RP, DIR>(u[p]);
+        }
         if constexpr (LAST) {
 #pragma unroll
-            for (int kk = 0; kk < RP; ++kk) out[i + kk * NB] = u[kk];
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int kk = 0; kk < RP; ++kk) out[p][i + kk * NB] = u[p][kk];
         } else {
             const int base = (b / NS) * NS * RP + k;
 #pragma unroll
-            for (int kk = 0; kk < RP; ++kk) lds[lds_slot(base + kk * NS)] = u[kk];
+            for (int kk = 0; kk < RP; ++kk) {
+                float2 x[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) x[p] = u[p][kk];
+                lds_put<P>(lds, lds_slot(base + kk * NS), x);
+            }
         }
     }
     if constexpr (LAST) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = out[r];
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int r = 0; r < E; ++r) v[p][r] = out[p][r];
     }
 }
 
-// Full transform. On entry v[r] = x[j + r*T]; on exit v[r] = X[j + r*T].
-// All threads of the block must call it (it contains block barriers).
-template <int M, int E, int DIR>
-__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
-    using P = Plan<M, E>;
-    constexpr int T = P::T;
+// Full transform of P sequences at once. On entry v[p][r] = x_p[j + r*T]; on exit
+// v[p][r] = X_p[j + r*T]. All threads of the block must call it (block barriers).
+template <int M, int E, int P, int DIR>
+__device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
+                                    const float2* __restrict__ tw) {
+    using PL = Plan<M, E>;
+    constexpr int T = PL::T;
     [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
         (([&] {
              constexpr int p = Ps;
-             constexpr int RP = P::radix(p);
-             constexpr int NS = P::ns(p);
-             constexpr bool LAST = (p == P::PASSES - 1);
-             stockham_pass<M, E, RP, NS, LAST, DIR>(v, lds, j, tw);
+             constexpr int RP = PL::radix(p);
+             constexpr int NS = PL::ns(p);
+             constexpr bool LAST = (p == PL::PASSES - 1);
+             stockham_pass<M, E, P, RP, NS, LAST, DIR>(v, lds, j, tw);
              if constexpr (!LAST) {
-                 __syncthreads();
+                 lds_barrier();
 #pragma unroll
-                 for (int r = 0; r < E; ++r) v[r] = lds[lds_slot(j + r * T)];
-                 __syncthreads();
+                 for (int r = 0; r < E; ++r) {
+                     float2 x[P];
+                     lds_get<P>(lds, lds_slot(j + r * T), x);
+#pragma unroll
+                     for (int q = 0; q < P; ++q) v[q][r] = x[q];
+                 }
+                 lds_barrier();
              }
          }()),
          ...);
-    }(std::make_integer_sequence<int, P::PASSES>{});
+    }(std::make_integer_sequence<int, PL::PASSES>{});
 }
 
 }  // namespace cwo

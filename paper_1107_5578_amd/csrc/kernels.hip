@@ -22,6 +22,7 @@
 //   Fresnel : H = C * Hx[p] * Hy[q]; the FFT of the sampled impulse response
 //             h_F factorises into two 1-D transforms of chirps, computed here
 //             in FP64 by direct summation.
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <utility>
@@ -33,6 +34,7 @@ namespace cwo {
 
 // ---- configuration per transform length --------------------------------------
 
+// Row passes: one transform per thread group of T = M/E threads, RPB rows per block.
 template <int M>
 struct RowCfg {
     static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
@@ -41,16 +43,23 @@ struct RowCfg {
     static constexpr int THREADS = T * RPB;
 };
 
+// Column pass: each thread transforms two adjacent columns (16-byte loads and
+// stores, one 16-byte LDS slot per element pair); PAIRS column pairs per block.
 template <int M>
 struct ColCfg {
     static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
     static constexpr int T = M / E;
-    // columns per block: keep the LDS exchange buffer near 72 KiB and at most 512 threads
-    static constexpr int BY_LDS = (72 * 1024) / (lds_elems<M>() * 8);
-    static constexpr int BY_THR = 512 / T;
-    static constexpr int C0 = BY_LDS < BY_THR ? BY_LDS : BY_THR;
-    static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);
-    static constexpr int THREADS = T * C;
+    // two columns per thread, except at M = 8192 where 32 values per column already
+    // fill the register budget
+    static constexpr int P = (M == 8192) ? 1 : 2;
+    static constexpr int LDS_PAIR = P * lds_elems<M>();  // float2 entries per pair
+    static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
+    static constexpr int BY_LDS0 = (72 * 1024) / (LDS_PAIR * 8);
+    static constexpr int BY_LDS = BY_LDS0 < 1 ? 1 : BY_LDS0;
+    static constexpr int PAIRS0 = BY_THR < BY_LDS ? BY_THR : BY_LDS;
+    static constexpr int PAIRS = PAIRS0 > 16 ? 16 : PAIRS0;
+    static constexpr int THREADS = T * PAIRS;
+    static constexpr int COLS = P * PAIRS;  // columns per block
 };
 
 // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs, which
@@ -77,53 +86,125 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
     const int sub = tid / T, j = tid % T;
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
-    const float2* src = in + blockIdx.y * in_plane + (size_t)row * nx;
-    float2 v[E];
+    const float2* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * nx;
+    float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int x = j + r * T;
         if constexpr (HALF) {
             // M == 2*nx: exactly the first E/2 registers hold field values
-            v[r] = (r < E / 2 && valid) ? src[x] : make_float2(0.f, 0.f);
+            v[0][r] = (r < E / 2 && valid) ? src[x] : make_float2(0.f, 0.f);
         } else {
-            v[r] = (valid && x < nx) ? src[x] : make_float2(0.f, 0.f);
+            v[0][r] = (valid && x < nx) ? src[x] : make_float2(0.f, 0.f);
         }
     }
-    fft<M, E, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
         float2* dst = out + blockIdx.y * out_plane + (size_t)row * M;
 #pragma unroll
-        for (int r = 0; r < E; ++r) dst[j + r * T] = v[r];
+        for (int r = 0; r < E; ++r) dst[j + r * T] = v[0][r];
     }
 }
 
 // ---- column pass: FFT, transfer function, IFFT, crop --------------------------
 
+// Exact form, for any parameters: per bin in FP64, the propagating test s <= 1
+// evaluated with the same operations as the FP64 reference, sine/cosine of the
+// reduced phase in FP32.
 struct AsmH {
     double dfx, dfy;  // frequency pitches 1/(Mx dx), 1/(My dy)
     double lam;       // wavelength
     double zl;        // z / lambda: phase in revolutions per unit sqrt(1 - s)
     int mx, my;
-    __device__ __forceinline__ float2 operator()(int p, int q) const {
+    struct Col {
+        double ax2;
+    };
+    __device__ __forceinline__ Col column(int p) const {
         const double pp = (double)(p < mx / 2 ? p : p - mx);
-        const double qq = (double)(q < my / 2 ? q : q - my);
-        // s = (lambda*fx)^2 + (lambda*fy)^2 with fx = p'*dfx, evaluated without contraction
         const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
+        return Col{__dmul_rn(ax, ax)};
+    }
+    struct Row {
+        double ay2;
+    };
+    __device__ __forceinline__ Row row(int q) const {
+        const double qq = (double)(q < my / 2 ? q : q - my);
         const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
-        const double s = __dadd_rn(__dmul_rn(ay, ay), __dmul_rn(ax, ax));
+        return Row{__dmul_rn(ay, ay)};
+    }
+    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
+        // s = (lambda*fx)^2 + (lambda*fy)^2 with fx = p'*dfx, evaluated without contraction
+        const double s = __dadd_rn(rw.ay2, c.ax2);
         if (!(s <= 1.0)) return make_float2(0.f, 0.f);  // evanescent bin
         const double t = zl * __dsqrt_rn(1.0 - s);       // revolutions
         const float r = (float)(t - rint(t));            // [-0.5, 0.5]
-        float sn, cs;
-        sincospif(2.0f * r, &sn, &cs);
-        return make_float2(cs, sn);
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+};
+
+// Fast form, used when every bin has s <= 0.05 (so none is evanescent). With
+// T(s) = 1 - s/2 - sqrt(1 - s), the phase in revolutions splits exactly into
+//     (z/lambda) sqrt(1 - s) = zl - zl*a/2 - zl*b/2 - zl*T(s),  s = a + b,
+// a = (lambda fx)^2 per column, b = (lambda fy)^2 per row. Every large term is
+// reduced modulo one revolution in FP64 before it is rounded to FP32; T(s) is the
+// power series sum_{n>=2} c_n s^n (c_n = (2n-3)!!/(2^n n!)) to n = 9, whose
+// truncation error is below 3e-12 relative for s <= 0.05. The hardware sine and
+// cosine take the reduced phase in revolutions.
+struct AsmHFast {
+    double lam_dfx, lam_dfy;  // lambda/(Mx dx), lambda/(My dy)
+    double zl, half_zl;       // z/lambda, z/(2 lambda)
+    float c0;                 // zl reduced to [-0.5, 0.5]
+    int mx, my;
+    struct Col {
+        double a;
+        float ca;  // c0 - reduced(zl*a/2)
+    };
+    __device__ __forceinline__ Col column(int p) const {
+        const double x = (double)(p < mx / 2 ? p : p - mx) * lam_dfx;
+        const double a = x * x;
+        const double ta = half_zl * a;
+        return Col{a, c0 - (float)(ta - rint(ta))};
+    }
+    struct Row {
+        double b, hb;  // (lambda fy)^2 and zl*b/2
+    };
+    __device__ __forceinline__ Row row(int q) const {
+        const double y = (double)(q < my / 2 ? q : q - my) * lam_dfy;
+        const double b = y * y;
+        return Row{b, half_zl * b};
+    }
+    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
+        const double s = c.a + rw.b;
+        double poly = 715.0 / 65536.0;
+        poly = fma(poly, s, 429.0 / 32768.0);
+        poly = fma(poly, s, 33.0 / 2048.0);
+        poly = fma(poly, s, 21.0 / 1024.0);
+        poly = fma(poly, s, 7.0 / 256.0);
+        poly = fma(poly, s, 5.0 / 128.0);
+        poly = fma(poly, s, 1.0 / 16.0);
+        poly = fma(poly, s, 1.0 / 8.0);
+        // zl*b/2 + zl*T(s), reduced, in FP64
+        const double u = fma(zl * (s * s), poly, rw.hb);
+        float r = c.ca - (float)(u - rint(u));
+        r -= rintf(r);
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
     }
 };
 
 struct FresnelH {
     const float2* __restrict__ hx;  // Mx entries, carries the constant C
     const float2* __restrict__ hy;  // My entries
-    __device__ __forceinline__ float2 operator()(int p, int q) const { return cmul(hx[p], hy[q]); }
+    struct Col {
+        float2 h;
+    };
+    struct Row {
+        float2 h;
+    };
+    __device__ __forceinline__ Col column(int p) const { return Col{hx[p]}; }
+    __device__ __forceinline__ Row row(int q) const { return Row{hy[q]}; }
+    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
+        return cmul(c.h, rw.h);
+    }
 };
 
 template <int M, bool HALF, class HF>
@@ -131,32 +212,52 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__
                                                               int mx, size_t plane, HF hf,
                                                               const float2* __restrict__ tw) {
     using C = ColCfg<M>;
-    constexpr int E = C::E, T = C::T;
-    __shared__ float2 lds[C::C * lds_elems<M>()];
+    constexpr int E = C::E, T = C::T, P = C::P;
+    __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
+    float2* lds = reinterpret_cast<float2*>(lds4);
     const int tid = threadIdx.x;
-    const int c = tid % C::C, j = tid / C::C;
+    const int pair = tid / T, j = tid % T;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int col = blk * C::C + c;  // mx is a multiple of C (both powers of two, C <= mx)
+    const int col0 = (blk * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
+    const bool active = col0 < mx;                 // blocks may overhang narrow planes
+    const int col = active ? col0 : 0;
     float2* base = buf + blockIdx.y * plane + col;
-    float2 v[E];
+    float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
-        if constexpr (HALF) v[r] = (r < E / 2) ? base[(size_t)y * mx] : make_float2(0.f, 0.f);
-        else v[r] = (y < ny) ? base[(size_t)y * mx] : make_float2(0.f, 0.f);
-    }
-    float2* my_lds = lds + c * lds_elems<M>();
-    fft<M, E, FWD>(v, my_lds, j, tw);
-#pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = cmul(v[r], hf(col, j + r * T));
-    fft<M, E, INV>(v, my_lds, j, tw);
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int y = j + r * T;
-        if constexpr (HALF) {
-            if (r < E / 2) base[(size_t)y * mx] = v[r];
+        const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
+        if constexpr (P == 2) {
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ld) t = *reinterpret_cast<const float4*>(base + (size_t)y * mx);
+            v[0][r] = make_float2(t.x, t.y);
+            v[1][r] = make_float2(t.z, t.w);
         } else {
-            if (y < ny) base[(size_t)y * mx] = v[r];
+            v[0][r] = ld ? base[(size_t)y * mx] : make_float2(0.f, 0.f);
+        }
+    }
+    float2* my_lds = lds + pair * C::LDS_PAIR;
+    typename HF::Col hc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
+    fft<M, E, P, FWD>(v, my_lds, j, tw);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const typename HF::Row hr = hf.row(j + r * T);
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[p][r] = cmul(v[p][r], hf(hc[p], hr));
+    }
+    fft<M, E, P, INV>(v, my_lds, j, tw);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int y = j + r * T;
+        const bool st = active && (HALF ? (r < E / 2) : (y < ny));
+        if (st) {
+            if constexpr (P == 2)
+                *reinterpret_cast<float4*>(base + (size_t)y * mx) =
+                    make_float4(v[0][r].x, v[0][r].y, v[1][r].x, v[1][r].y);
+            else
+                base[(size_t)y * mx] = v[0][r];
         }
     }
 }
@@ -177,16 +278,16 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(const float2* __
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
     const float2* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * M;
-    float2 v[E];
+    float2 v[1][E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = valid ? src[j + r * T] : make_float2(0.f, 0.f);
-    fft<M, E, INV>(v, lds + sub * lds_elems<M>(), j, tw);
+    for (int r = 0; r < E; ++r) v[0][r] = valid ? src[j + r * T] : make_float2(0.f, 0.f);
+    fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
         float2* dst = out + blockIdx.y * out_plane + (size_t)row * nx;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int x = j + r * T;
-            const float2 o = make_float2(v[r].x * scale, v[r].y * scale);
+            const float2 o = make_float2(v[0][r].x * scale, v[0][r].y * scale);
             if constexpr (HALF) {
                 if (r < E / 2) dst[x] = o;
             } else {
@@ -264,18 +365,18 @@ __global__ __launch_bounds__(256) void k_chirp_dft(const double2* __restrict__ h
 
 // ---- host launchers ------------------------------------------------------------
 
-#define CWO_DISPATCH_M(M_, BODY)              \
+#define CWO_DISPATCH_M(M_, ...)              \
     switch (M_) {                             \
-        case 16: { constexpr int MM = 16; BODY; } break;     \
-        case 32: { constexpr int MM = 32; BODY; } break;     \
-        case 64: { constexpr int MM = 64; BODY; } break;     \
-        case 128: { constexpr int MM = 128; BODY; } break;   \
-        case 256: { constexpr int MM = 256; BODY; } break;   \
-        case 512: { constexpr int MM = 512; BODY; } break;   \
-        case 1024: { constexpr int MM = 1024; BODY; } break; \
-        case 2048: { constexpr int MM = 2048; BODY; } break; \
-        case 4096: { constexpr int MM = 4096; BODY; } break; \
-        case 8192: { constexpr int MM = 8192; BODY; } break; \
+        case 16: { constexpr int MM = 16; __VA_ARGS__; } break;     \
+        case 32: { constexpr int MM = 32; __VA_ARGS__; } break;     \
+        case 64: { constexpr int MM = 64; __VA_ARGS__; } break;     \
+        case 128: { constexpr int MM = 128; __VA_ARGS__; } break;   \
+        case 256: { constexpr int MM = 256; __VA_ARGS__; } break;   \
+        case 512: { constexpr int MM = 512; __VA_ARGS__; } break;   \
+        case 1024: { constexpr int MM = 1024; __VA_ARGS__; } break; \
+        case 2048: { constexpr int MM = 2048; __VA_ARGS__; } break; \
+        case 4096: { constexpr int MM = 4096; __VA_ARGS__; } break; \
+        case 8192: { constexpr int MM = 8192; __VA_ARGS__; } break; \
         default: return hipErrorInvalidValue;                 \
     }
 
@@ -306,8 +407,7 @@ static hipError_t launch_col_impl(float2* buf, int ny, int my, int mx, int batch
     const bool half = (my == 2 * ny);
     CWO_DISPATCH_M(my, {
         using C = ColCfg<MM>;
-        if (mx % C::C != 0) return hipErrorInvalidValue;
-        dim3 grid(mx / C::C, batch);
+        dim3 grid((mx + C::COLS - 1) / C::COLS, batch);
         if (half)
             hipLaunchKernelGGL((k_col<MM, true, HF>), grid, dim3(C::THREADS), 0, s, buf, ny, mx,
                                plane, hf, tw);
@@ -320,6 +420,20 @@ static hipError_t launch_col_impl(float2* buf, int ny, int my, int mx, int batch
 
 hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
                           const AsmScalars& a, const float2* tw, hipStream_t s) {
+    // largest s = (lambda fx)^2 + (lambda fy)^2 on the grid: the Nyquist corner
+    const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
+    const double smax = sx * sx + sy * sy;
+    if (smax <= kAsmFastMaxS) {
+        AsmHFast hf;
+        hf.lam_dfx = a.lam * a.dfx;
+        hf.lam_dfy = a.lam * a.dfy;
+        hf.zl = a.zl;
+        hf.half_zl = 0.5 * a.zl;
+        hf.c0 = (float)(a.zl - std::nearbyint(a.zl));
+        hf.mx = mx;
+        hf.my = my;
+        return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
+    }
     AsmH hf{a.dfx, a.dfy, a.lam, a.zl, mx, my};
     return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
 }

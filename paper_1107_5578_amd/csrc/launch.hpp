@@ -13,6 +13,10 @@ struct AsmScalars {
     double zl;        // z / wavelength
 };
 
+// The angular-spectrum column pass takes the fast phase form when every bin of the
+// grid has (lambda fx)^2 + (lambda fy)^2 <= this bound, the exact FP64 form otherwise.
+constexpr double kAsmFastMaxS = 0.05;
+
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s);
 
 // in: batch planes of [ny][nx] (plane stride in_plane elements); out: [ny][mx] per plane
