@@ -76,6 +76,25 @@ def cpu_baseline(u_np, cfg, kind="asm", min_seconds: float = 10.0, max_planes: i
                            % (done, u_np.shape[1], u_np.shape[0], kind, threads, dt)}
 
 
+def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm):
+    """Planes/s of one z-stack call (all planes) over `reps` calls, HIP events."""
+    out = torch.empty((len(zs),) + tuple(u.shape), dtype=torch.complex64, device=u.device)
+    for _ in range(warm):
+        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(u.device)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del out
+    return len(zs) * 1000.0 / ms, ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +105,8 @@ def main():
                     help="transfer function of the timed plane (the headline metric is asm)")
     ap.add_argument("--n", type=int, default=0,
                     help="field size other than the headline 2048 (a side measurement)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the z-stack (batched form) measurements")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (a plain copy "
                          "kernel of known traffic, to calibrate profiler byte counters)")
@@ -152,6 +173,23 @@ def main():
                 "plane_alg_bytes": sum(sb.values()),
                 "plane_GBps": round(sum(sb.values()) / (ms_per_step * 1e-3) / 1e9, 1)}
 
+    batched = None
+    if not args.no_batched and args.kind == "asm":
+        # batched form: the same field to 64 distances in one cwo_zstack call, against the
+        # same 64 distances as 64 plain calls (the plain figure above is one distance)
+        zs = list(W.zstack_distances(64, 0.05, 0.5))
+        z_pps, z_ms = time_zstack(ctx, torch, u, zs, cfg.pitch, cfg.wavelength, 5, 2)
+        batched = {"form": "cwo_zstack, one %dx%d field to 64 distances in [0.05, 0.5] m" % (n, n),
+                   "planes_per_s": round(z_pps, 1), "ms_per_stack": round(z_ms, 4),
+                   "vs_plain": round(z_pps / value, 3)}
+        c3 = W.ZSTACK_1024
+        u3 = torch.from_numpy(W.field_for(c3)).to(dev)
+        z3 = list(W.zstack_distances(64, 0.05, 0.2))
+        c3_pps, c3_ms = time_zstack(ctx, torch, u3, z3, c3.pitch, c3.wavelength, 10, 2)
+        batched["zstack_1024x64"] = {"planes_per_s": round(c3_pps, 1), "ms_per_stack": round(c3_ms, 4),
+                                     "workload": "1024x1024 speckle, 4um, 633nm, 64 z in [0.05, 0.2] m"}
+        del u3
+
     y = out.cpu().numpy()
     line = {
         "metric": "%s planes/s at %d^2 fp32 (plain per-call form)" % (args.kind.upper(), n),
@@ -175,6 +213,8 @@ def main():
                     for k, v in kernels.items()},
         "roofline": roofline,
     }
+    if batched is not None:
+        line["batched"] = batched
     if not args.no_cpu_baseline:
         ref, base = cpu_baseline(u_np, cfg, args.kind)
         from oracle import diffraction as D

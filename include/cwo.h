@@ -22,7 +22,7 @@
  * (the paper's single-precision cwoComplex field). All field pointers are DEVICE pointers
  * owned by the caller; the library never frees them. in == out is allowed.
  *
- * Ordering: cwo_asm / cwo_fresnel / cwo_zstack / cwo_gs are asynchronous and ordered on the
+ * Ordering: cwo_asm / cwo_fresnel / cwo_zstack / cwo_batch are asynchronous and ordered on the
  * given HIP stream (hipStream_t passed as void*, NULL = the null stream); they return
  * after enqueueing. Calls on one context share its scratch memory: serialise them
  * (one stream, or external synchronisation). cwo_submit / cwo_poll are thread-safe.
@@ -74,6 +74,14 @@ typedef struct {
     uint32_t flags;      /* CWO_FLAG_* */
 } cwo_params;
 
+/* One propagation request: parameters plus device pointers (caller-owned complex64
+ * [ny][nx]). */
+typedef struct {
+    cwo_params p;
+    const void* in;
+    void* out;
+} cwo_job;
+
 typedef struct cwo_ctx cwo_ctx; /* opaque */
 
 /* Create a context on HIP device `device`. hbm_budget_bytes bounds the scratch memory the
@@ -94,6 +102,24 @@ cwo_status cwo_asm(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
 cwo_status cwo_fresnel(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
                        void* hip_stream);
 
+/* z-stack: one field propagated to nz distances, the paper's 3-D field built by stacking
+ * 2-D propagations (Sec. 2.3, Diffract3D). p->kind selects CWO_ANGULAR or
+ * CWO_FRESNEL_CONV (0 is CWO_ERR_INVALID here); p->z is ignored; z is a HOST array of nz
+ * distances (each validated like p->z). out holds nz planes [nz][ny][nx] complex64 on the
+ * device. The row transform of the field and the forward column transforms are done once;
+ * planes are processed in chunks of at most 64 that fit the context's budget
+ * (CWO_ERR_NOMEM if not even one plane fits). Plane k equals cwo_asm / cwo_fresnel with
+ * z = z[k] up to rounding order. */
+cwo_status cwo_zstack(cwo_ctx* ctx, const cwo_params* p, const double* z, int32_t nz,
+                      const void* in, void* out, void* hip_stream);
+
+/* Batch of independent jobs, stream-ordered, in order. Consecutive jobs on the same input
+ * pointer with equal geometry, wavelength, kind, precision and flags are run as one
+ * z-stack (their outputs may be anywhere); every other job runs as a single propagation.
+ * Each job's p.kind must be CWO_ANGULAR or CWO_FRESNEL_CONV. All jobs are validated before
+ * anything is launched. */
+cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip_stream);
+
 /* Validate a parameter set for `kind` without touching any device: the same checks the
  * propagation calls run first. Returns CWO_OK, CWO_ERR_INVALID or CWO_ERR_UNSUPPORTED. */
 cwo_status cwo_check_params(const cwo_params* p, int32_t kind);
@@ -106,7 +132,8 @@ typedef enum {
     CWO_STAGE_ROW_FWD = 0,   /* zero-pad + forward row FFT */
     CWO_STAGE_COL = 1,       /* column FFT, transfer function, inverse column FFT, crop */
     CWO_STAGE_ROW_INV = 2,   /* inverse row FFT + crop + 1/(Mx My) */
-    CWO_STAGE_TABLES = 3,    /* twiddle and Fresnel transfer-vector generation */
+    CWO_STAGE_TABLES = 3,    /* Fresnel transfer-vector generation */
+    CWO_STAGE_COL_Z = 4,     /* z-stack column pass: one forward FFT, per plane H x IFFT */
     CWO_STAGE_COUNT = 8
 } cwo_stage;
 

@@ -1,6 +1,7 @@
 // Host runtime of libcwo: contexts, validation, tables, scratch and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -34,6 +35,13 @@ struct FresnelEntry {
     float2* h = nullptr;  // mx + my complex64: Hx (with C) then Hy
 };
 
+// A device buffer that only grows; growing waits for the device first because
+// queued kernels on any stream may still use the old allocation.
+struct Buffer {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
 }  // namespace
 
 struct cwo_ctx {
@@ -42,10 +50,9 @@ struct cwo_ctx {
     std::mutex mu;
     cwo_status sticky = CWO_OK;
     std::map<int, float2*> twiddles;  // FP32 exp(-2 pi i k / M) per M
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
-    double2* fres_work = nullptr;  // 2*M FP64 complex for the chirp transforms
-    int fres_work_m = 0;
+    Buffer scratch;                   // padded planes
+    Buffer fwork;                     // FP64 chirps and twiddles for the Fresnel factors
+    Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     std::list<FresnelEntry> fresnel;  // most recently used first
     // per-kernel timing
     bool profiling = false;
@@ -110,8 +117,8 @@ hipError_t drain_profile(cwo_ctx* c) {
     return err;
 }
 
-#define CWO_HIP(ctx, call)                          \
-    do {                                            \
+#define CWO_HIP(ctx, call)                              \
+    do {                                                \
         if ((call) != hipSuccess) return dev_fail(ctx); \
     } while (0)
 
@@ -134,39 +141,40 @@ const float2* twiddle_table(cwo_ctx* c, int m, hipStream_t s, cwo_status* st) {
     return tw;
 }
 
-void* ensure_scratch(cwo_ctx* c, size_t bytes, cwo_status* st) {
-    if (c->scratch_bytes >= bytes) return c->scratch;
-    if (c->budget && bytes > c->budget) {
+size_t held_bytes(const cwo_ctx* c) { return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes; }
+
+void* ensure(cwo_ctx* c, Buffer& b, size_t bytes, cwo_status* st) {
+    if (b.bytes >= bytes) return b.p;
+    if (c->budget && held_bytes(c) - b.bytes + bytes > c->budget) {
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
-    if (c->scratch) {
-        // the old buffer may still be read by queued kernels on any stream
+    if (b.p) {
         if (hipDeviceSynchronize() != hipSuccess) {
             *st = dev_fail(c);
             return nullptr;
         }
-        (void)hipFree(c->scratch);
-        c->scratch = nullptr;
-        c->scratch_bytes = 0;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
     }
-    if (hipMalloc(&c->scratch, bytes) != hipSuccess) {
-        c->scratch = nullptr;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
-    c->scratch_bytes = bytes;
-    return c->scratch;
+    b.bytes = bytes;
+    return b.p;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-cwo_status validate(const cwo_params* p, int kind) {
+// Everything except the distance.
+cwo_status validate_geometry(const cwo_params* p, int kind) {
     if (!p) return CWO_ERR_INVALID;
+    if (kind != CWO_ANGULAR && kind != CWO_FRESNEL_CONV) return CWO_ERR_INVALID;
     if (p->kind != 0 && p->kind != kind) return CWO_ERR_INVALID;
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
-    if (!std::isfinite(p->z)) return CWO_ERR_INVALID;
-    if (kind == CWO_FRESNEL_CONV && p->z == 0.0) return CWO_ERR_INVALID;
     if ((p->flags & ~(uint32_t)CWO_FLAG_NOPAD) != 0) return CWO_ERR_INVALID;
     if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
     if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
@@ -176,6 +184,18 @@ cwo_status validate(const cwo_params* p, int kind) {
     return CWO_OK;
 }
 
+cwo_status validate_z(double z, int kind) {
+    if (!std::isfinite(z)) return CWO_ERR_INVALID;
+    if (kind == CWO_FRESNEL_CONV && z == 0.0) return CWO_ERR_INVALID;
+    return CWO_OK;
+}
+
+cwo_status validate(const cwo_params* p, int kind) {
+    cwo_status st = validate_geometry(p, kind);
+    if (st != CWO_OK) return st;
+    return validate_z(p->z, kind);
+}
+
 struct Geometry {
     int nx, ny, mx, my;
 };
@@ -183,6 +203,15 @@ struct Geometry {
 Geometry geometry(const cwo_params* p) {
     const bool nopad = (p->flags & CWO_FLAG_NOPAD) != 0;
     return Geometry{p->nx, p->ny, nopad ? p->nx : 2 * p->nx, nopad ? p->ny : 2 * p->ny};
+}
+
+cwo::AsmScalars asm_scalars(const cwo_params* p, const Geometry& g, double z) {
+    cwo::AsmScalars a;
+    a.dfx = 1.0 / ((double)g.mx * p->dx);
+    a.dfy = 1.0 / ((double)g.my * p->dy);
+    a.lam = p->wavelength;
+    a.zl = z / p->wavelength;
+    return a;
 }
 
 // exp(i k z) / (i lambda z) * dx * dy, with k z reduced in revolutions in FP64
@@ -196,6 +225,24 @@ void fresnel_constant(double dx, double dy, double lam, double z, double* re, do
     *im = -amp * std::cos(ang);
 }
 
+cwo::FresnelPlanes fresnel_planes(const cwo_params* p, const Geometry& g, const double* z, int nz) {
+    cwo::FresnelPlanes fp;
+    std::memset(&fp, 0, sizeof(fp));
+    fp.mx = g.mx;
+    fp.nx = g.nx;
+    fp.my = g.my;
+    fp.ny = g.ny;
+    fp.dx = p->dx;
+    fp.dy = p->dy;
+    fp.nz = nz;
+    for (int k = 0; k < nz; ++k) {
+        fp.inv2lz[k] = 0.5 / (p->wavelength * z[k]);
+        fresnel_constant(p->dx, p->dy, p->wavelength, z[k], &fp.cre[k], &fp.cim[k]);
+    }
+    return fp;
+}
+
+// Fresnel factors of one plane, cached per parameter set.
 const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g, hipStream_t s,
                               cwo_status* st) {
     FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z};
@@ -205,27 +252,10 @@ const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g
             return c->fresnel.front().h;
         }
     }
-    const int mmax = g.mx > g.my ? g.mx : g.my;
-    if (c->fres_work_m < mmax) {
-        if (c->fres_work) {
-            if (hipDeviceSynchronize() != hipSuccess) {
-                *st = dev_fail(c);
-                return nullptr;
-            }
-            (void)hipFree(c->fres_work);
-            c->fres_work = nullptr;
-            c->fres_work_m = 0;
-        }
-        if (hipMalloc(&c->fres_work, sizeof(double2) * 2 * (size_t)mmax) != hipSuccess) {
-            *st = CWO_ERR_NOMEM;
-            return nullptr;
-        }
-        c->fres_work_m = mmax;
-    }
-    FresnelEntry e;
-    e.key = key;
+    const size_t len = (size_t)(g.mx + g.my);
+    double2* work = (double2*)ensure(c, c->fwork, sizeof(double2) * len * 2, st);
+    if (!work) return nullptr;
     if (c->fresnel.size() >= kFresnelCacheEntries) {
-        // reuse the least recently used buffer if it is large enough
         FresnelEntry old = c->fresnel.back();
         c->fresnel.pop_back();
         if (hipDeviceSynchronize() != hipSuccess) {
@@ -234,20 +264,16 @@ const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g
         }
         (void)hipFree(old.h);
     }
-    if (hipMalloc(&e.h, sizeof(float2) * (size_t)(g.mx + g.my)) != hipSuccess) {
+    FresnelEntry e;
+    e.key = key;
+    if (hipMalloc(&e.h, sizeof(float2) * len) != hipSuccess) {
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
-    double cre, cim;
-    fresnel_constant(p->dx, p->dy, p->wavelength, p->z, &cre, &cim);
-    const double lz = p->wavelength * p->z;
-    // the chirp work buffer is reused by consecutive launches on the same stream
-    hipError_t herr = timed(c, CWO_STAGE_TABLES, s, [&] {
-        hipError_t e1 = cwo::launch_fresnel_axis(c->fres_work, e.h, g.mx, g.nx, p->dx, lz, cre, cim, s);
-        if (e1 != hipSuccess) return e1;
-        return cwo::launch_fresnel_axis(c->fres_work, e.h + g.mx, g.my, g.ny, p->dy, lz, 1.0, 0.0, s);
-    });
-    if (herr != hipSuccess) {
+    const double z = p->z;
+    const cwo::FresnelPlanes fp = fresnel_planes(p, g, &z, 1);
+    if (timed(c, CWO_STAGE_TABLES, s, [&] { return cwo::launch_fresnel_planes(work, e.h, fp, s); }) !=
+        hipSuccess) {
         (void)hipFree(e.h);
         *st = dev_fail(c);
         return nullptr;
@@ -256,40 +282,38 @@ const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g
     return e.h;
 }
 
-cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
-                     void* stream) {
-    if (!c) return CWO_ERR_INVALID;
-    cwo_status st = validate(p, kind);
-    if (st != CWO_OK) return st;
-    if (!in || !out) return CWO_ERR_INVALID;
-    std::lock_guard<std::mutex> lock(c->mu);
+cwo_status begin(cwo_ctx* c) {
     if (c->sticky != CWO_OK) return c->sticky;
-    CWO_HIP(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return dev_fail(c);
+    return CWO_OK;
+}
+
+cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
+                            hipStream_t s) {
+    cwo_status st = CWO_OK;
     const Geometry g = geometry(p);
     const float2* twx = twiddle_table(c, g.mx, s, &st);
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    float2* buf = (float2*)ensure_scratch(c, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    float2* buf = (float2*)ensure(c, c->scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
     if (!buf) return st;
     const float2* fin = (const float2*)in;
     float2* fout = (float2*)out;
+    const float2* h = nullptr;
+    if (kind == CWO_FRESNEL_CONV) {
+        h = fresnel_factors(c, p, g, s, &st);
+        if (!h) return st;
+    }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
                 return cwo::launch_row_fwd(fin, buf, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
             }));
     if (kind == CWO_ANGULAR) {
-        cwo::AsmScalars a;
-        a.dfx = 1.0 / ((double)g.mx * p->dx);
-        a.dfy = 1.0 / ((double)g.my * p->dy);
-        a.lam = p->wavelength;
-        a.zl = p->z / p->wavelength;
+        const cwo::AsmScalars a = asm_scalars(p, g, p->z);
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, twy, s);
                 }));
     } else {
-        const float2* h = fresnel_factors(c, p, g, s, &st);
-        if (!h) return st;
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, 1, 0, h, h + g.mx, twy, s);
                 }));
@@ -299,6 +323,93 @@ cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, 
                 return cwo::launch_row_inv(buf, fout, g.nx, g.ny, g.mx, 1, 0, 0, scale, twx, s);
             }));
     return CWO_OK;
+}
+
+cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
+                     void* stream) {
+    if (!c) return CWO_ERR_INVALID;
+    cwo_status st = validate(p, kind);
+    if (st != CWO_OK) return st;
+    if (!in || !out) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = begin(c);
+    if (st != CWO_OK) return st;
+    return propagate_locked(c, p, kind, in, out, (hipStream_t)stream);
+}
+
+// One field to nz distances; plane k goes to outs[k]. The row transform of the field
+// and the forward column transforms run once; planes are processed in chunks of at
+// most kZChunk that fit the scratch budget.
+cwo_status zstack_locked(cwo_ctx* c, const cwo_params* p, int kind, const double* z, int nz,
+                         const void* in, void* const* outs, hipStream_t s) {
+    cwo_status st = CWO_OK;
+    const Geometry g = geometry(p);
+    const float2* twx = twiddle_table(c, g.mx, s, &st);
+    if (!twx) return st;
+    const float2* twy = twiddle_table(c, g.my, s, &st);
+    if (!twy) return st;
+    const size_t plane = (size_t)g.ny * g.mx;
+    const size_t len = (size_t)(g.mx + g.my);
+    // chunk size: the shared spectrum and all planes of a chunk within the budget
+    int zc = std::min(nz, cwo::kZChunk);
+    if (c->budget) {
+        const size_t fres = kind == CWO_FRESNEL_CONV ? (sizeof(float2) + sizeof(double2)) * len : 0;
+        const size_t per_plane = sizeof(float2) * plane + fres;
+        const size_t base = sizeof(float2) * plane + (kind == CWO_FRESNEL_CONV ? sizeof(double2) * len : 0);
+        if (c->budget < base + per_plane) return CWO_ERR_NOMEM;
+        const size_t fit = (c->budget - base) / per_plane;
+        zc = (int)std::min<size_t>((size_t)zc, fit);
+    }
+    float2* buf = (float2*)ensure(c, c->scratch, sizeof(float2) * plane * (size_t)(1 + zc), &st);
+    if (!buf) return st;
+    float2* spec = buf;
+    float2* zbuf = buf + plane;
+    float2* tabs = nullptr;
+    double2* work = nullptr;
+    if (kind == CWO_FRESNEL_CONV) {
+        tabs = (float2*)ensure(c, c->ftab, sizeof(float2) * len * zc, &st);
+        if (!tabs) return st;
+        work = (double2*)ensure(c, c->fwork, sizeof(double2) * len * (zc + 1), &st);
+        if (!work) return st;
+    }
+    CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
+                return cwo::launch_row_fwd((const float2*)in, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
+            }));
+    const float scale = 1.0f / ((float)g.mx * (float)g.my);
+    for (int k0 = 0; k0 < nz; k0 += zc) {
+        const int n = std::min(zc, nz - k0);
+        cwo::ZChunk ch;
+        std::memset(&ch, 0, sizeof(ch));
+        ch.nz = n;
+        for (int k = 0; k < n; ++k) {
+            ch.zl[k] = z[k0 + k] / p->wavelength;
+            ch.out[k] = (float2*)outs[k0 + k];
+        }
+        if (kind == CWO_ANGULAR) {
+            const cwo::AsmScalars a = asm_scalars(p, g, 0.0);
+            CWO_HIP(c, timed(c, CWO_STAGE_COL_Z, s, [&] {
+                        return cwo::launch_col_z_asm(spec, zbuf, g.ny, g.my, g.mx, plane, a, ch, twy, s);
+                    }));
+        } else {
+            const cwo::FresnelPlanes fp = fresnel_planes(p, g, z + k0, n);
+            CWO_HIP(c, timed(c, CWO_STAGE_TABLES, s,
+                             [&] { return cwo::launch_fresnel_planes(work, tabs, fp, s); }));
+            CWO_HIP(c, timed(c, CWO_STAGE_COL_Z, s, [&] {
+                        return cwo::launch_col_z_fresnel(spec, zbuf, g.ny, g.my, g.mx, plane, tabs, n,
+                                                         twy, s);
+                    }));
+        }
+        CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
+                    return cwo::launch_row_inv_z(zbuf, ch, g.nx, g.ny, g.mx, plane, scale, twx, s);
+                }));
+    }
+    return CWO_OK;
+}
+
+bool same_group(const cwo_job& a, const cwo_job& b) {
+    return a.in == b.in && a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx &&
+           a.p.dy == b.p.dy && a.p.wavelength == b.p.wavelength && a.p.kind == b.p.kind &&
+           a.p.precision == b.p.precision && a.p.flags == b.p.flags;
 }
 
 }  // namespace
@@ -325,11 +436,11 @@ cwo_status cwo_destroy(cwo_ctx* c) {
         std::lock_guard<std::mutex> lock(c->mu);
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
+        (void)drain_profile(c);
         for (auto& kv : c->twiddles) (void)hipFree(kv.second);
         for (auto& e : c->fresnel) (void)hipFree(e.h);
-        if (c->scratch) (void)hipFree(c->scratch);
-        if (c->fres_work) (void)hipFree(c->fres_work);
-        (void)drain_profile(c);
+        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab})
+            if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
     }
     delete c;
@@ -342,6 +453,55 @@ cwo_status cwo_asm(cwo_ctx* c, const cwo_params* p, const void* in, void* out, v
 
 cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* out, void* stream) {
     return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream);
+}
+
+cwo_status cwo_zstack(cwo_ctx* c, const cwo_params* p, const double* z, int32_t nz, const void* in,
+                      void* out, void* stream) {
+    if (!c || !p || !z || !in || !out || nz < 1) return CWO_ERR_INVALID;
+    const int kind = p->kind;
+    cwo_status st = validate_geometry(p, kind);
+    if (st != CWO_OK) return st;
+    for (int k = 0; k < nz; ++k)
+        if ((st = validate_z(z[k], kind)) != CWO_OK) return st;
+    const Geometry g = geometry(p);
+    std::vector<void*> outs((size_t)nz);
+    for (int k = 0; k < nz; ++k) outs[k] = (float2*)out + (size_t)k * g.ny * g.nx;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if ((st = begin(c)) != CWO_OK) return st;
+    return zstack_locked(c, p, kind, z, nz, in, outs.data(), (hipStream_t)stream);
+}
+
+cwo_status cwo_batch(cwo_ctx* c, const cwo_job* jobs, int32_t njobs, void* stream) {
+    if (!c || (!jobs && njobs > 0) || njobs < 0) return CWO_ERR_INVALID;
+    cwo_status st;
+    for (int i = 0; i < njobs; ++i) {
+        if ((st = validate(&jobs[i].p, jobs[i].p.kind)) != CWO_OK) return st;
+        if (!jobs[i].in || !jobs[i].out) return CWO_ERR_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(c->mu);
+    if ((st = begin(c)) != CWO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // consecutive jobs on the same field and geometry form one z-stack
+    int i = 0;
+    while (i < njobs) {
+        int j = i + 1;
+        while (j < njobs && same_group(jobs[i], jobs[j])) ++j;
+        if (j - i == 1) {
+            st = propagate_locked(c, &jobs[i].p, jobs[i].p.kind, jobs[i].in, jobs[i].out, s);
+        } else {
+            std::vector<double> z;
+            std::vector<void*> outs;
+            for (int k = i; k < j; ++k) {
+                z.push_back(jobs[k].p.z);
+                outs.push_back(jobs[k].out);
+            }
+            st = zstack_locked(c, &jobs[i].p, jobs[i].p.kind, z.data(), j - i, jobs[i].in,
+                               outs.data(), s);
+        }
+        if (st != CWO_OK) return st;
+        i = j;
+    }
+    return CWO_OK;
 }
 
 cwo_status cwo_profile(cwo_ctx* c, int32_t enable) {
@@ -367,15 +527,11 @@ cwo_status cwo_profile_read(cwo_ctx* c, int32_t stage, double* total_ms, int64_t
     return CWO_OK;
 }
 
-cwo_status cwo_check_params(const cwo_params* p, int32_t kind) {
-    if (kind != CWO_ANGULAR && kind != CWO_FRESNEL_CONV) return CWO_ERR_INVALID;
-    return validate(p, kind);
-}
+cwo_status cwo_check_params(const cwo_params* p, int32_t kind) { return validate(p, kind); }
 
 size_t cwo_scratch_bytes(const cwo_params* p) {
     if (!p) return 0;
     const int kind = p->kind == 0 ? CWO_ANGULAR : p->kind;
-    if (kind != CWO_ANGULAR && kind != CWO_FRESNEL_CONV) return 0;
     if (validate(p, kind) != CWO_OK) return 0;
     const Geometry g = geometry(p);
     return sizeof(float2) * (size_t)g.ny * (size_t)g.mx;

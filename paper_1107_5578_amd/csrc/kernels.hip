@@ -62,6 +62,23 @@ struct ColCfg {
     static constexpr int COLS = P * PAIRS;  // columns per block
 };
 
+// z-stack column pass: the forward spectrum stays in registers while each plane's
+// inverse transform runs on a copy, so one column per thread.
+template <int M>
+struct ZColCfg {
+    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
+    static constexpr int T = M / E;
+    static constexpr int P = 1;
+    static constexpr int LDS_PAIR = lds_elems<M>();
+    static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
+    static constexpr int BY_LDS0 = (72 * 1024) / (LDS_PAIR * 8);
+    static constexpr int BY_LDS = BY_LDS0 < 1 ? 1 : BY_LDS0;
+    static constexpr int PAIRS0 = BY_THR < BY_LDS ? BY_THR : BY_LDS;
+    static constexpr int PAIRS = PAIRS0 > 16 ? 16 : PAIRS0;
+    static constexpr int THREADS = T * PAIRS;
+    static constexpr int COLS = P * PAIRS;
+};
+
 // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs, which
 // have separate L2 caches. Remap so that each XCD works on a contiguous range
 // of tiles; neighbouring tiles share cache lines.
@@ -262,13 +279,182 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__
     }
 }
 
-// ---- row inverse: IFFT + crop + normalisation ---------------------------------
+// ---- z-stack column pass ------------------------------------------------------
+//
+// One field, many distances: the forward column transform is done once per column
+// pair and kept in registers; for each plane the spectrum is multiplied by that
+// plane's transfer function and inverse transformed into the plane's scratch.
+
+// The z-independent part of each bin is computed once, after the forward column
+// transform, and kept in a register across the plane loop; each plane then costs
+// one FP64 multiply and a reduction per bin.
+//
+// Fast form (every bin s <= 0.05): K = 1 - sqrt(1 - s) = s/2 + T(s) from the same
+// series as AsmHFast; the phase of plane z is zl - zl*K revolutions, i.e.
+// reduce(zl) - reduce(zl*K). Exact form: Q = sqrt(1 - s) in FP64 (Q < 0 marks an
+// evanescent bin, s > 1, decided with the reference's operations); the phase is zl*Q.
+struct AsmZFast {
+    double lam_dfx, lam_dfy;
+    int mx, my;
+    __device__ __forceinline__ double bin(int p, int q) const {
+        const double x = (double)(p < mx / 2 ? p : p - mx) * lam_dfx;
+        const double y = (double)(q < my / 2 ? q : q - my) * lam_dfy;
+        const double s = x * x + y * y;
+        double poly = 715.0 / 65536.0;
+        poly = fma(poly, s, 429.0 / 32768.0);
+        poly = fma(poly, s, 33.0 / 2048.0);
+        poly = fma(poly, s, 21.0 / 1024.0);
+        poly = fma(poly, s, 7.0 / 256.0);
+        poly = fma(poly, s, 5.0 / 128.0);
+        poly = fma(poly, s, 1.0 / 16.0);
+        poly = fma(poly, s, 1.0 / 8.0);
+        return fma(s * s, poly, 0.5 * s);
+    }
+    __device__ __forceinline__ float2 at(double k, double zl, float c0) const {
+        const double u = zl * k;
+        float r = c0 - (float)(u - rint(u));
+        r -= rintf(r);
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+};
+
+struct AsmZExact {
+    double dfx, dfy, lam;
+    int mx, my;
+    __device__ __forceinline__ double bin(int p, int q) const {
+        const double pp = (double)(p < mx / 2 ? p : p - mx);
+        const double qq = (double)(q < my / 2 ? q : q - my);
+        const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
+        const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
+        const double s = __dadd_rn(__dmul_rn(ay, ay), __dmul_rn(ax, ax));
+        return (s <= 1.0) ? __dsqrt_rn(1.0 - s) : -1.0;
+    }
+    __device__ __forceinline__ float2 at(double qv, double zl, float) const {
+        if (qv < 0.0) return make_float2(0.f, 0.f);
+        const double t = zl * qv;
+        const float r = (float)(t - rint(t));
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+};
+
+template <class ZH>
+struct ZSetAsm {
+    ZH h;
+    double zl[kZChunk];
+    int nz;
+};
+
+struct ZSetFresnel {
+    const float2* h;  // plane k: Hx (with C) at h + k*stride, Hy at h + k*stride + mx
+    size_t stride;
+    int mx, nz;
+};
 
 template <int M, bool HALF>
+__device__ __forceinline__ void zcol_load(const float2* __restrict__ src, int ny, int mx, int j,
+                                          bool active, float2 (&v)[1][ZColCfg<M>::E]) {
+    using C = ZColCfg<M>;
+    constexpr int E = C::E, T = C::T;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int y = j + r * T;
+        const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
+        v[0][r] = ld ? src[(size_t)y * mx] : make_float2(0.f, 0.f);
+    }
+}
+
+template <int M, bool HALF>
+__device__ __forceinline__ void zcol_store(float2* __restrict__ dst, int ny, int mx, int j,
+                                           bool active, const float2 (&w)[1][ZColCfg<M>::E]) {
+    using C = ZColCfg<M>;
+    constexpr int E = C::E, T = C::T;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int y = j + r * T;
+        const bool st = active && (HALF ? (r < E / 2) : (y < ny));
+        if (st) dst[(size_t)y * mx] = w[0][r];
+    }
+}
+
+template <int M, bool HALF, class ZH>
+__global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
+    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
+    ZSetAsm<ZH> zs, const float2* __restrict__ tw) {
+    using C = ZColCfg<M>;
+    constexpr int E = C::E, T = C::T;
+    __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int col0 = blk * C::PAIRS + sub;
+    const bool active = col0 < mx;
+    const int col = active ? col0 : 0;
+    float2* my_lds = lds + sub * C::LDS_PAIR;
+    float2 v[1][E];
+    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
+    fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    double kb[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) kb[r] = zs.h.bin(col, j + r * T);
+    for (int k = 0; k < zs.nz; ++k) {
+        const float2* twk = tw;  // opaque per plane: twiddles are reloaded, not kept live
+        asm volatile("" : "+s"(twk));
+        const double zl = zs.zl[k];
+        const float c0 = (float)(zl - rint(zl));
+        float2 w[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(kb[r], zl, c0));
+        fft<M, E, 1, INV>(w, my_lds, j, twk);
+        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + col, ny, mx, j, active, w);
+    }
+}
+
+template <int M, bool HALF>
+__global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
+    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
+    ZSetFresnel zs, const float2* __restrict__ tw) {
+    using C = ZColCfg<M>;
+    constexpr int E = C::E, T = C::T;
+    __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int col0 = blk * C::PAIRS + sub;
+    const bool active = col0 < mx;
+    const int col = active ? col0 : 0;
+    float2* my_lds = lds + sub * C::LDS_PAIR;
+    float2 v[1][E];
+    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
+    fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    for (int k = 0; k < zs.nz; ++k) {
+        const float2* twk = tw;
+        asm volatile("" : "+s"(twk));
+        const float2* hk = zs.h + (size_t)k * zs.stride;
+        const float2 hx = hk[col];
+        float2 w[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], cmul(hx, hk[zs.mx + j + r * T]));
+        fft<M, E, 1, INV>(w, my_lds, j, twk);
+        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + col, ny, mx, j, active, w);
+    }
+}
+
+// ---- row inverse: IFFT + crop + normalisation ---------------------------------
+
+struct OutStrided {
+    float2* out;
+    size_t plane;
+    __device__ __forceinline__ float2* operator()(int k) const { return out + k * plane; }
+};
+struct OutTable {
+    float2* out[kZChunk];
+    __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
+};
+
+template <int M, bool HALF, class OUT>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(const float2* __restrict__ in,
-                                                                  float2* __restrict__ out, int nx,
-                                                                  int ny, size_t in_plane,
-                                                                  size_t out_plane, float scale,
+                                                                  OUT outs, int nx, int ny,
+                                                                  size_t in_plane, float scale,
                                                                   const float2* __restrict__ tw) {
     using C = RowCfg<M>;
     constexpr int E = C::E, T = C::T;
@@ -283,7 +469,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(const float2* __
     for (int r = 0; r < E; ++r) v[0][r] = valid ? src[j + r * T] : make_float2(0.f, 0.f);
     fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
-        float2* dst = out + blockIdx.y * out_plane + (size_t)row * nx;
+        float2* dst = outs(blockIdx.y) + (size_t)row * nx;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int x = j + r * T;
@@ -308,58 +494,75 @@ __global__ void k_twiddles(float2* tw, int m) {
     tw[k] = make_float2((float)c, (float)(-s));
 }
 
-// Sampled 1-D chirp of the Fresnel impulse response on the padded axis:
-// h[d] = exp(i * a * (s(d)*pitch)^2), s(d) = d for d < n, d - m otherwise,
-// a = pi/(lambda z); the phase is evaluated in revolutions (a/pi)(...)/2 and reduced.
-__global__ void k_chirp(double2* h, int m, int n, double pitch, double half_rev_per_m2) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= m) return;
-    const double off = (double)(d < n ? d : d - m) * pitch;
-    const double t = half_rev_per_m2 * (off * off);  // revolutions = (1/(2 lambda z)) x^2
+// ---- Fresnel transfer-function factors ---------------------------------------
+//
+// The FFT of the sampled impulse response h_F(m, n) = hx(m) hy(n) is the outer
+// product of two 1-D transforms, each computed here in FP64 by direct summation
+// with an FP64 twiddle table (index (p*d) mod M, so every twiddle is exact to an ulp).
+
+// chirp[k][i]: axis x for i < mx (d = i), axis y for i >= mx (d = i - mx);
+// h[d] = exp(i*pi*(s(d)*pitch)^2/(lambda z_k)) with s(d) = d for d < n, d - m otherwise.
+// The phase in revolutions, (s(d) pitch)^2 / (2 lambda z_k), is reduced in FP64.
+__global__ void k_chirps(double2* chirp, FresnelPlanes fp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const int len = fp.mx + fp.my;
+    if (i >= len) return;
+    const bool xa = i < fp.mx;
+    const int d = xa ? i : i - fp.mx;
+    const int m = xa ? fp.mx : fp.my, n = xa ? fp.nx : fp.ny;
+    const double off = (double)(d < n ? d : d - m) * (xa ? fp.dx : fp.dy);
+    const double t = fp.inv2lz[k] * (off * off);
     const double r = t - rint(t);
-    double s, c;
-    sincospi(2.0 * r, &s, &c);
-    h[d] = make_double2(c, s);
+    double sn, cs;
+    sincospi(2.0 * r, &sn, &cs);
+    chirp[(size_t)k * len + i] = make_double2(cs, sn);
 }
 
-// tw64[k] = exp(-2*pi*i*k/M) in FP64 (for the FP64 chirp transforms)
-__global__ void k_twiddles64(double2* tw, int m) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    double s, c;
-    sincospi(2.0 * (double)k / (double)m, &s, &c);
-    tw[k] = make_double2(c, -s);
+// tw64[i] = exp(-2*pi*i*d/m) for the x axis (i < mx) then the y axis
+__global__ void k_twiddles64(double2* tw, int mx, int my) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mx + my) return;
+    const bool xa = i < mx;
+    const int d = xa ? i : i - mx, m = xa ? mx : my;
+    double sn, cs;
+    sincospi(2.0 * (double)d / (double)m, &sn, &cs);
+    tw[i] = make_double2(cs, -sn);
 }
 
-// Hx[p] = coef * sum_d h[d] * exp(-2*pi*i*((p*d) mod m)/m), FP64 accumulation.
-// One block of 256 threads per output bin.
-__global__ __launch_bounds__(256) void k_chirp_dft(const double2* __restrict__ h,
+// out[k][i] = coef * sum_d chirp[k][d] * tw[(p*d) mod m], one block of 256 threads per
+// output bin (axis x carries C_k, axis y carries 1).
+__global__ __launch_bounds__(256) void k_chirp_dft(const double2* __restrict__ chirp,
                                                    const double2* __restrict__ tw64,
-                                                   float2* __restrict__ out, int m, double coef_re,
-                                                   double coef_im) {
+                                                   float2* __restrict__ out, FresnelPlanes fp) {
     __shared__ double red[2][256];
-    const int p = blockIdx.x;
+    const int i = blockIdx.x, k = blockIdx.y;
+    const int len = fp.mx + fp.my;
+    const bool xa = i < fp.mx;
+    const int p = xa ? i : i - fp.mx, m = xa ? fp.mx : fp.my;
+    const double2* h = chirp + (size_t)k * len + (xa ? 0 : fp.mx);
+    const double2* w = tw64 + (xa ? 0 : fp.mx);
     double ar = 0.0, ai = 0.0;
     for (int d = threadIdx.x; d < m; d += 256) {
-        const int idx = (int)(((long long)p * d) & (m - 1));
-        const double2 w = tw64[idx];
+        const double2 wd = w[(int)(((long long)p * d) & (m - 1))];
         const double2 x = h[d];
-        ar += x.x * w.x - x.y * w.y;
-        ai += x.x * w.y + x.y * w.x;
+        ar += x.x * wd.x - x.y * wd.y;
+        ai += x.x * wd.y + x.y * wd.x;
     }
     red[0][threadIdx.x] = ar;
     red[1][threadIdx.x] = ai;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + st];
+            red[1][threadIdx.x] += red[1][threadIdx.x + st];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const double sr = red[0][0], si = red[1][0];
-        out[p] = make_float2((float)(sr * coef_re - si * coef_im), (float)(sr * coef_im + si * coef_re));
+        const double cr = xa ? fp.cre[k] : 1.0, ci = xa ? fp.cim[k] : 0.0;
+        out[(size_t)k * len + i] = make_float2((float)(sr * cr - si * ci), (float)(sr * ci + si * cr));
     }
 }
 
@@ -444,34 +647,101 @@ hipError_t launch_col_fresnel(float2* buf, int ny, int my, int mx, int batch, si
     return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
 }
 
-hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx, int batch,
-                          size_t in_plane, size_t out_plane, float scale, const float2* tw,
-                          hipStream_t s) {
+template <class OUT>
+static hipError_t launch_row_inv_impl(const float2* in, const OUT& outs, int nx, int ny, int mx,
+                                      int batch, size_t in_plane, float scale, const float2* tw,
+                                      hipStream_t s) {
     const bool half = (mx == 2 * nx);
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
         if (half)
-            hipLaunchKernelGGL((k_row_inv<MM, true>), grid, dim3(C::THREADS), 0, s, in, out, nx, ny,
-                               in_plane, out_plane, scale, tw);
+            hipLaunchKernelGGL((k_row_inv<MM, true, OUT>), grid, dim3(C::THREADS), 0, s, in, outs,
+                               nx, ny, in_plane, scale, tw);
         else
-            hipLaunchKernelGGL((k_row_inv<MM, false>), grid, dim3(C::THREADS), 0, s, in, out, nx,
-                               ny, in_plane, out_plane, scale, tw);
+            hipLaunchKernelGGL((k_row_inv<MM, false, OUT>), grid, dim3(C::THREADS), 0, s, in, outs,
+                               nx, ny, in_plane, scale, tw);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_fresnel_axis(double2* work, float2* out, int m, int n, double pitch,
-                               double lam_z, double coef_re, double coef_im, hipStream_t s) {
-    // work holds 2*m FP64 complex values: the chirp, then the FP64 twiddle table
-    const double half_rev_per_m2 = 0.5 / lam_z;  // pi/(lambda z) rad = 1/(2 lambda z) rev
+hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, float scale, const float2* tw,
+                          hipStream_t s) {
+    return launch_row_inv_impl(in, OutStrided{out, out_plane}, nx, ny, mx, batch, in_plane, scale,
+                               tw, s);
+}
+
+hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
+                            size_t zplane, float scale, const float2* tw, hipStream_t s) {
+    OutTable t;
+    for (int k = 0; k < kZChunk; ++k) t.out[k] = k < zc.nz ? zc.out[k] : nullptr;
+    return launch_row_inv_impl(zbuf, t, nx, ny, mx, zc.nz, zplane, scale, tw, s);
+}
+
+template <class ZH>
+static hipError_t launch_col_z_asm_impl(const float2* spec, float2* zbuf, int ny, int my, int mx,
+                                        size_t zplane, const ZSetAsm<ZH>& zs, const float2* tw,
+                                        hipStream_t s) {
+    const bool half = (my == 2 * ny);
+    CWO_DISPATCH_M(my, {
+        using C = ZColCfg<MM>;
+        dim3 grid((mx + C::COLS - 1) / C::COLS);
+        if (half)
+            hipLaunchKernelGGL((k_col_z_asm<MM, true, ZH>), grid, dim3(C::THREADS), 0, s, spec,
+                               zbuf, ny, mx, zplane, zs, tw);
+        else
+            hipLaunchKernelGGL((k_col_z_asm<MM, false, ZH>), grid, dim3(C::THREADS), 0, s, spec,
+                               zbuf, ny, mx, zplane, zs, tw);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, int mx,
+                            size_t zplane, const AsmScalars& a, const ZChunk& zc,
+                            const float2* tw, hipStream_t s) {
+    const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
+    if (sx * sx + sy * sy <= kAsmFastMaxS) {
+        ZSetAsm<AsmZFast> zs;
+        zs.h = AsmZFast{a.lam * a.dfx, a.lam * a.dfy, mx, my};
+        for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
+        zs.nz = zc.nz;
+        return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
+    }
+    ZSetAsm<AsmZExact> zs;
+    zs.h = AsmZExact{a.dfx, a.dfy, a.lam, mx, my};
+    for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
+    zs.nz = zc.nz;
+    return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
+}
+
+hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my, int mx,
+                                size_t zplane, const float2* h, int nz, const float2* tw,
+                                hipStream_t s) {
+    ZSetFresnel zs{h, (size_t)(mx + my), mx, nz};
+    const bool half = (my == 2 * ny);
+    CWO_DISPATCH_M(my, {
+        using C = ZColCfg<MM>;
+        dim3 grid((mx + C::COLS - 1) / C::COLS);
+        if (half)
+            hipLaunchKernelGGL((k_col_z_fresnel<MM, true>), grid, dim3(C::THREADS), 0, s, spec,
+                               zbuf, ny, mx, zplane, zs, tw);
+        else
+            hipLaunchKernelGGL((k_col_z_fresnel<MM, false>), grid, dim3(C::THREADS), 0, s, spec,
+                               zbuf, ny, mx, zplane, zs, tw);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
+                                 hipStream_t s) {
+    const int len = fp.mx + fp.my;
     double2* chirp = work;
-    double2* tw64 = work + m;
-    hipLaunchKernelGGL(k_twiddles64, dim3((m + 255) / 256), dim3(256), 0, s, tw64, m);
-    hipLaunchKernelGGL(k_chirp, dim3((m + 255) / 256), dim3(256), 0, s, chirp, m, n, pitch,
-                       half_rev_per_m2);
-    hipLaunchKernelGGL(k_chirp_dft, dim3(m), dim3(256), 0, s, (const double2*)chirp,
-                       (const double2*)tw64, out, m, coef_re, coef_im);
+    double2* tw64 = work + (size_t)len * fp.nz;
+    hipLaunchKernelGGL(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);
+    hipLaunchKernelGGL(k_chirps, dim3((len + 255) / 256, fp.nz), dim3(256), 0, s, chirp, fp);
+    hipLaunchKernelGGL(k_chirp_dft, dim3(len, fp.nz), dim3(256), 0, s, (const double2*)chirp,
+                       (const double2*)tw64, out, fp);
     return hipGetLastError();
 }
 

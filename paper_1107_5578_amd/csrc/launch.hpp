@@ -17,6 +17,17 @@ struct AsmScalars {
 // grid has (lambda fx)^2 + (lambda fy)^2 <= this bound, the exact FP64 form otherwise.
 constexpr double kAsmFastMaxS = 0.05;
 
+// Up to this many planes per z-stack launch (per-plane scalars and output pointers
+// travel as kernel arguments).
+constexpr int kZChunk = 64;
+
+// Per-plane scalars of one z-stack chunk.
+struct ZChunk {
+    int nz;
+    double zl[kZChunk];      // z / lambda of each plane (ASM)
+    float2* out[kZChunk];    // destination field of each plane, [ny][nx]
+};
+
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s);
 
 // in: batch planes of [ny][nx] (plane stride in_plane elements); out: [ny][mx] per plane
@@ -34,9 +45,32 @@ hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx,
                           size_t in_plane, size_t out_plane, float scale, const float2* tw,
                           hipStream_t s);
 
-// One axis of the Fresnel transfer function: out[p] = coef * DFT_m(chirp)[p], FP64 inside.
-// work must hold 2*m double2.
-hipError_t launch_fresnel_axis(double2* work, float2* out, int m, int n, double pitch,
-                               double lam_z, double coef_re, double coef_im, hipStream_t s);
+// z-stack column pass: spec holds the row spectra [ny][mx] of one field (read only);
+// for each plane k < zc.nz the column spectrum is multiplied by H(z_k), inverse
+// transformed and written to zbuf + k * zplane ([ny][mx] each).
+hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, int mx,
+                            size_t zplane, const AsmScalars& a, const ZChunk& zc,
+                            const float2* tw, hipStream_t s);
+// Fresnel: the 1-D factors of plane k are at h + k * (mx + my) (Hx with C, then Hy).
+hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my, int mx,
+                                size_t zplane, const float2* h, int nz, const float2* tw,
+                                hipStream_t s);
+// Row inverse of zc.nz planes of zbuf into the per-plane outputs zc.out[k].
+hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
+                            size_t zplane, float scale, const float2* tw, hipStream_t s);
+
+// Fresnel transfer-function factors of up to kZChunk planes that share the geometry:
+// plane k gets Hx_k = C_k * DFT_mx(hx_k) at out + k*(mx+my) and Hy_k = DFT_my(hy_k) right
+// after it, where h*_k are the sampled 1-D chirps exp(i pi (s(d) pitch)^2 / (lambda z_k)).
+struct FresnelPlanes {
+    int mx, nx, my, ny;
+    double dx, dy;
+    int nz;
+    double inv2lz[kZChunk];       // 1 / (2 lambda z_k): chirp phase in revolutions per m^2
+    double cre[kZChunk], cim[kZChunk];  // C_k = dx dy exp(i k z_k) / (i lambda z_k)
+};
+// work must hold (mx + my) * (nz + 1) double2 (chirps, then the FP64 twiddle tables).
+hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
+                                 hipStream_t s);
 
 }  // namespace cwo

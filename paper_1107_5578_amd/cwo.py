@@ -40,8 +40,10 @@ STAGE_ROW_FWD = 0
 STAGE_COL = 1
 STAGE_ROW_INV = 2
 STAGE_TABLES = 3
+STAGE_COL_Z = 4
 STAGE_NAMES = {STAGE_ROW_FWD: "row_fwd", STAGE_COL: "col", STAGE_ROW_INV: "row_inv",
-               STAGE_TABLES: "tables"}
+               STAGE_TABLES: "tables", STAGE_COL_Z: "col_z"}
+KINDS = {"asm": ANGULAR, "angular": ANGULAR, "fresnel": FRESNEL_CONV}
 
 
 class CwoError(RuntimeError):
@@ -61,6 +63,10 @@ class Params(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("p", Params), ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -72,6 +78,11 @@ SIGNATURES = {
                                  ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_zstack": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int32,
+                                   ctypes.c_void_p]),
     "cwo_check_params": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.c_int32]),
     "cwo_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "cwo_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -203,6 +214,50 @@ class Context:
         """Fresnel diffraction (convolution form) by z."""
         return self._propagate(self._lib.cwo_fresnel, FRESNEL_CONV, u, dx, dy, wavelength, z,
                                precision, nopad, out, stream)
+
+
+    def zstack(self, u, z, dx=10e-6, dy=None, wavelength=633e-9, kind="asm", precision="f32",
+               nopad=False, out=None, stream=None):
+        """Propagate one field to every distance in z; returns [nz, ny, nx] planes."""
+        import torch
+        u = self._field(u)
+        ny, nx = u.shape
+        zs = [float(v) for v in z]
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        p = make_params(nx, ny, dx, dy, wavelength, 0.0, k, precision, nopad)
+        if out is None:
+            out = torch.empty((len(zs), ny, nx), dtype=torch.complex64, device=u.device)
+        elif (out.dtype != torch.complex64 or tuple(out.shape) != (len(zs), ny, nx)
+              or not out.is_contiguous() or out.device != u.device):
+            raise ValueError("out must be a contiguous complex64 [nz, ny, nx] tensor")
+        zarr = (ctypes.c_double * max(len(zs), 1))(*zs)
+        st = self._lib.cwo_zstack(self.handle, ctypes.byref(p), zarr, len(zs),
+                                  ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_zstack")
+        return out
+
+    def batch(self, jobs, stream=None):
+        """Run a list of (kind, u, out, dict(dx=, dy=, wavelength=, z=, ...)) jobs in order."""
+        if not jobs:
+            return
+        arr = (Job * len(jobs))()
+        first = None
+        for i, (kind, u, out, kw) in enumerate(jobs):
+            u = self._field(u)
+            out = self._field(out)
+            first = first if first is not None else u
+            ny, nx = u.shape
+            k = KINDS[kind] if isinstance(kind, str) else int(kind)
+            arr[i].p = make_params(nx, ny, kw.get("dx", 10e-6), kw.get("dy"),
+                                   kw.get("wavelength", 633e-9), kw.get("z", 0.1), k,
+                                   kw.get("precision", "f32"), kw.get("nopad", False))
+            arr[i].inp = u.data_ptr()
+            arr[i].out = out.data_ptr()
+        st = self._lib.cwo_batch(self.handle, arr, len(jobs), self._stream(first, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_batch")
 
 
 _default = {}

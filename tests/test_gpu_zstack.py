@@ -1,0 +1,162 @@
+"""GPU parity of the z-stack (one field, many distances) and the batch entry point.
+
+Every plane of a stack is compared with the single-plane call of the same distance
+(same kernels for the shared forward part; the inverse part differs only in
+instruction scheduling, so agreement is expected to rounding level) and with the
+FP64 oracle (relative L2 <= 1e-5 per plane, element-wise <= 1e-5 of the plane's peak).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1107_5578_amd import cwo
+    c = cwo.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def check(y, ref, label, rel_tol=1e-5, elem_tol=1e-5):
+    rl = D.rel_l2(y, ref)
+    peak = float(np.max(np.abs(ref)))
+    emax = float(np.max(np.abs(y.astype(np.complex128) - ref)))
+    note("%s rel_l2=%.3e max_abs_err/peak=%.3e" % (label, rl, emax / peak))
+    assert rl <= rel_tol, (label, rl)
+    assert emax <= elem_tol * peak, (label, emax / peak)
+
+
+def single(ctx, kind, t, dx, lam, z):
+    fn = ctx.asm if kind == "asm" else ctx.fresnel
+    return fn(t, dx, dx, lam, z)
+
+
+def test_zstack_1024_64_planes(ctx):
+    import torch
+    cfg = W.ZSTACK_1024
+    u = W.field_for(cfg)
+    zs = W.zstack_distances(64, 0.05, 0.2)
+    note("zstack asm n=1024 nz=64 pitch=%g lam=%g" % (cfg.pitch, cfg.wavelength))
+    t = torch.from_numpy(u).cuda()
+    stack = ctx.zstack(t, zs, cfg.pitch, cfg.pitch, cfg.wavelength, kind="asm")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, z in enumerate(zs):
+        one = single(ctx, "asm", t, cfg.pitch, cfg.wavelength, z)
+        torch.cuda.synchronize()
+        worst = max(worst, D.rel_l2(stack[k].cpu().numpy(), one.cpu().numpy().astype(np.complex128)))
+    note("zstack vs single calls: worst rel_l2 = %.3e" % worst)
+    assert worst <= 1e-6
+    for k in (0, 21, 42, 63):
+        ref = D.asm(u, cfg.pitch, cfg.pitch, cfg.wavelength, zs[k])
+        check(stack[k].cpu().numpy(), ref, "zstack-1024 plane %d" % k)
+
+
+@pytest.mark.parametrize("kind", ["asm", "fresnel"])
+@pytest.mark.parametrize("n,ny", [(256, 256), (64, 128), (2048, 2048)])
+def test_zstack_sizes(ctx, kind, n, ny):
+    import torch
+    u = W.uniform_random_field(n, n + ny, ny=ny)
+    zs = [0.02, -0.05, 0.11, 0.3, 0.5] if kind == "asm" else [0.02, -0.05, 0.11, 0.3]
+    note("zstack %s %dx%d nz=%d" % (kind, n, ny, len(zs)))
+    t = torch.from_numpy(u).cuda()
+    stack = ctx.zstack(t, zs, 8e-6, 8e-6, 532e-9, kind=kind)
+    torch.cuda.synchronize()
+    for k, z in enumerate(zs):
+        one = single(ctx, kind, t, 8e-6, 532e-9, z).cpu().numpy()
+        assert D.rel_l2(stack[k].cpu().numpy(), one.astype(np.complex128)) <= 1e-6
+    for k in (0, len(zs) - 1):
+        ref = D.propagate(u, kind, 8e-6, 8e-6, 532e-9, zs[k])
+        check(stack[k].cpu().numpy(), ref, "zstack-%s-%dx%d plane %d" % (kind, n, ny, k))
+
+
+def test_zstack_exact_phase_path(ctx):
+    # 0.6 um pitch at 633 nm: s reaches 2*(lambda/2dx)^2 = 0.56 > 0.05, so the stack takes
+    # the exact per-bin FP64 form (and evanescent bins appear at the corners)
+    import torch
+    u = W.uniform_random_field(128, 77)
+    zs = [1e-5, 3e-5, -2e-5]
+    t = torch.from_numpy(u).cuda()
+    stack = ctx.zstack(t, zs, 0.6e-6, 0.6e-6, 633e-9, kind="asm")
+    torch.cuda.synchronize()
+    for k, z in enumerate(zs):
+        check(stack[k].cpu().numpy(), D.asm(u, 0.6e-6, 0.6e-6, 633e-9, z), "exact-z plane %d" % k)
+
+
+def test_zstack_chunked_by_budget(ctx):
+    # a budget that holds the spectrum and two planes forces chunks of two
+    import torch
+    from paper_1107_5578_amd import cwo
+    n = 128
+    plane = 8 * n * 2 * n
+    small = cwo.Context(0, hbm_budget_bytes=3 * plane)
+    try:
+        u = torch.from_numpy(W.uniform_random_field(n, 5)).cuda()
+        zs = [0.01 * (k + 1) for k in range(7)]
+        a = small.zstack(u, zs, 10e-6, 10e-6, 633e-9, kind="asm")
+        b = ctx.zstack(u, zs, 10e-6, 10e-6, 633e-9, kind="asm")
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        tiny = cwo.Context(0, hbm_budget_bytes=plane)
+        with pytest.raises(cwo.CwoError) as e:
+            tiny.zstack(u, zs, 10e-6, 10e-6, 633e-9, kind="asm")
+        assert e.value.status == cwo.CWO_ERR_NOMEM
+        tiny.close()
+    finally:
+        small.close()
+
+
+def test_batch_mixed(ctx):
+    import torch
+    u1 = torch.from_numpy(W.uniform_random_field(256, 1)).cuda()
+    u2 = torch.from_numpy(W.uniform_random_field(512, 2)).cuda()
+    u3 = torch.from_numpy(W.uniform_random_field(64, 3, ny=32)).cuda()
+    jobs = []
+    outs = []
+    spec = [("asm", u1, dict(dx=10e-6, wavelength=633e-9, z=0.1)),
+            ("asm", u1, dict(dx=10e-6, wavelength=633e-9, z=0.2)),
+            ("asm", u1, dict(dx=10e-6, wavelength=633e-9, z=-0.05)),
+            ("fresnel", u2, dict(dx=8e-6, wavelength=532e-9, z=0.3)),
+            ("fresnel", u2, dict(dx=8e-6, wavelength=532e-9, z=0.4)),
+            ("asm", u3, dict(dx=4e-6, wavelength=473e-9, z=0.01)),
+            ("fresnel", u1, dict(dx=10e-6, wavelength=633e-9, z=0.1))]
+    for kind, u, kw in spec:
+        o = torch.empty_like(u)
+        outs.append(o)
+        jobs.append((kind, u, o, kw))
+    ctx.batch(jobs)
+    torch.cuda.synchronize()
+    for (kind, u, kw), o in zip(spec, outs):
+        one = (ctx.asm if kind == "asm" else ctx.fresnel)(u, kw["dx"], kw["dx"], kw["wavelength"],
+                                                          kw["z"])
+        torch.cuda.synchronize()
+        assert D.rel_l2(o.cpu().numpy(), one.cpu().numpy().astype(np.complex128)) <= 1e-6
+    ref = D.fresnel(u2.cpu().numpy(), 8e-6, 8e-6, 532e-9, 0.4)
+    check(outs[4].cpu().numpy(), ref, "batch fresnel 512")
+
+
+def test_batch_validation_before_launch(ctx):
+    import torch
+    from paper_1107_5578_amd import cwo
+    u = torch.from_numpy(W.uniform_random_field(64, 1)).cuda()
+    o = torch.zeros_like(u)
+    with pytest.raises(cwo.CwoError) as e:
+        ctx.batch([("asm", u, o, dict(z=0.1)), ("fresnel", u, torch.zeros_like(u), dict(z=0.0))])
+    assert e.value.status == cwo.CWO_ERR_INVALID
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(o).item() == 0   # nothing ran
