@@ -107,6 +107,8 @@ def main():
                     help="field size other than the headline 2048 (a side measurement)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the z-stack (batched form) measurements")
+    ap.add_argument("--no-gs", action="store_true",
+                    help="skip the ping-pong (GS) iteration measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (a plain copy "
                          "kernel of known traffic, to calibrate profiler byte counters)")
@@ -190,6 +192,30 @@ def main():
                                      "workload": "1024x1024 speckle, 4um, 633nm, 64 z in [0.05, 0.2] m"}
         del u3
 
+    gs = None
+    if not args.no_gs and args.kind == "asm" and n == cfg.n:
+        # 200 ping-pong iterations (400 propagations) between two 2048^2 planes 0.1 m apart
+        a1, a2, u0 = W.gs_problem(2048)
+        ta1 = torch.from_numpy(a1).to(dev)
+        ta2 = torch.from_numpy(a2).to(dev)
+        tu = torch.from_numpy(u0).to(dev)
+        g = W.GS_2048
+        ctx.gs(tu.clone(), ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=5)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        errs = ctx.gs(tu, ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=200)
+        b.record(stream)
+        torch.cuda.synchronize()
+        gms = a.elapsed_time(b)
+        e = errs.cpu().numpy()
+        gs = {"workload": "2048x2048 rectangles targets 0.1 m apart, 8um, 532nm, 200 iterations",
+              "ms_total": round(gms, 3), "ms_per_iteration": round(gms / 200, 4),
+              "propagations_per_s": round(400 * 1000.0 / gms, 1),
+              "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
+        del ta1, ta2, tu
+
     y = out.cpu().numpy()
     line = {
         "metric": "%s planes/s at %d^2 fp32 (plain per-call form)" % (args.kind.upper(), n),
@@ -215,6 +241,8 @@ def main():
     }
     if batched is not None:
         line["batched"] = batched
+    if gs is not None:
+        line["gs_pingpong"] = gs
     if not args.no_cpu_baseline:
         ref, base = cpu_baseline(u_np, cfg, args.kind)
         from oracle import diffraction as D

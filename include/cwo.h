@@ -120,6 +120,19 @@ cwo_status cwo_zstack(cwo_ctx* ctx, const cwo_params* p, const double* z, int32_
  * anything is launched. */
 cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip_stream);
 
+/* Amplitude-constrained ping-pong iteration between two planes a distance p->z apart, by
+ * the angular spectrum method (the Gerchberg-Saxton loop of Sec. 7.2 with an amplitude
+ * target at both planes; a1 == 1 gives the paper's kinoform variant). One iteration:
+ *     v = ASM_{+z}(u);  E_k = || |v| - a2 ||_2 / || a2 ||_2;  v <- a2 v/|v|  (a2 where v == 0)
+ *     w = ASM_{-z}(v);  u <- a1 w/|w|  (a1 where w == 0)
+ * u: device complex64 [ny][nx], the start field on entry and u after `iterations` steps on
+ * exit. a1, a2: device float32 [ny][nx] amplitudes. errors: device float32[iterations]
+ * receiving E_k, or NULL. p->kind must be 0 or CWO_ANGULAR. Each propagation is one
+ * column pass plus one fused row pass (inverse row FFT, crop, constraint, re-pad,
+ * forward row FFT). Scratch: ny * 2nx complex64, plus iterations * ny doubles for E_k. */
+cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
+                  int32_t iterations, float* errors, void* hip_stream);
+
 /* Validate a parameter set for `kind` without touching any device: the same checks the
  * propagation calls run first. Returns CWO_OK, CWO_ERR_INVALID or CWO_ERR_UNSUPPORTED. */
 cwo_status cwo_check_params(const cwo_params* p, int32_t kind);
@@ -134,6 +147,7 @@ typedef enum {
     CWO_STAGE_ROW_INV = 2,   /* inverse row FFT + crop + 1/(Mx My) */
     CWO_STAGE_TABLES = 3,    /* Fresnel transfer-vector generation */
     CWO_STAGE_COL_Z = 4,     /* z-stack column pass: one forward FFT, per plane H x IFFT */
+    CWO_STAGE_ROW_GS = 5,    /* ping-pong row pass: IFFT, crop, constraint, pad, FFT */
     CWO_STAGE_COUNT = 8
 } cwo_stage;
 

@@ -1,6 +1,6 @@
 """Oracle: amplitude-constrained ping-pong iteration (test infrastructure only).
 
-The Gerchberg-Saxton style loop of the paper's GS application (Sec. 5.2,
+The Gerchberg-Saxton style loop of the paper's GS application (Sec. 7.2,
 "GS algorithm"): the field is propagated by the angular spectrum method to a
 plane at distance z, an amplitude constraint is imposed there, the field is
 propagated back by -z, and a constraint is imposed at the start plane.

@@ -53,6 +53,7 @@ struct cwo_ctx {
     Buffer scratch;                   // padded planes
     Buffer fwork;                     // FP64 chirps and twiddles for the Fresnel factors
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
+    Buffer gsnum;                     // per-row error partials of the ping-pong iteration
     std::list<FresnelEntry> fresnel;  // most recently used first
     // per-kernel timing
     bool profiling = false;
@@ -141,7 +142,9 @@ const float2* twiddle_table(cwo_ctx* c, int m, hipStream_t s, cwo_status* st) {
     return tw;
 }
 
-size_t held_bytes(const cwo_ctx* c) { return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes; }
+size_t held_bytes(const cwo_ctx* c) {
+    return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes + c->gsnum.bytes;
+}
 
 void* ensure(cwo_ctx* c, Buffer& b, size_t bytes, cwo_status* st) {
     if (b.bytes >= bytes) return b.p;
@@ -439,7 +442,7 @@ cwo_status cwo_destroy(cwo_ctx* c) {
         (void)drain_profile(c);
         for (auto& kv : c->twiddles) (void)hipFree(kv.second);
         for (auto& e : c->fresnel) (void)hipFree(e.h);
-        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab})
+        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab, &c->gsnum})
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
     }
@@ -500,6 +503,56 @@ cwo_status cwo_batch(cwo_ctx* c, const cwo_job* jobs, int32_t njobs, void* strea
         }
         if (st != CWO_OK) return st;
         i = j;
+    }
+    return CWO_OK;
+}
+
+cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float* a2, void* u,
+                  int32_t iterations, float* errors, void* stream) {
+    if (!c || !a1 || !a2 || !u || iterations < 0) return CWO_ERR_INVALID;
+    cwo_status st = validate(p, CWO_ANGULAR);
+    if (st != CWO_OK) return st;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if ((st = begin(c)) != CWO_OK) return st;
+    if (iterations == 0) return CWO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const Geometry g = geometry(p);
+    const float2* twx = twiddle_table(c, g.mx, s, &st);
+    if (!twx) return st;
+    const float2* twy = twiddle_table(c, g.my, s, &st);
+    if (!twy) return st;
+    float2* spec = (float2*)ensure(c, c->scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    if (!spec) return st;
+    double* num = nullptr;
+    if (errors) {
+        num = (double*)ensure(c, c->gsnum, sizeof(double) * ((size_t)iterations * g.ny + 1), &st);
+        if (!num) return st;
+    }
+    const cwo::AsmScalars fwd = asm_scalars(p, g, p->z), back = asm_scalars(p, g, -p->z);
+    const float scale = 1.0f / ((float)g.mx * (float)g.my);
+    float2* field = (float2*)u;
+    CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
+                return cwo::launch_row_fwd(field, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
+            }));
+    for (int k = 0; k < iterations; ++k) {
+        CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, fwd, twy, s);
+                }));
+        double* nk = num ? num + (size_t)k * g.ny : nullptr;
+        CWO_HIP(c, timed(c, CWO_STAGE_ROW_GS, s, [&] {
+                    return cwo::launch_row_gs(spec, a2, nullptr, nk, g.nx, g.ny, g.mx, scale, twx, s);
+                }));
+        CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, back, twy, s);
+                }));
+        float2* dst = (k == iterations - 1) ? field : nullptr;
+        CWO_HIP(c, timed(c, CWO_STAGE_ROW_GS, s, [&] {
+                    return cwo::launch_row_gs(spec, a1, dst, nullptr, g.nx, g.ny, g.mx, scale, twx, s);
+                }));
+    }
+    if (errors) {
+        double* den = num + (size_t)iterations * g.ny;
+        CWO_HIP(c, cwo::launch_gs_errors(num, a2, den, errors, g.nx, g.ny, iterations, s));
     }
     return CWO_OK;
 }

@@ -59,6 +59,18 @@ hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my
 hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
                             size_t zplane, float scale, const float2* tw, hipStream_t s);
 
+// Ping-pong iteration row kernel. For each of the ny rows of spec ([ny][mx], the output
+// of a column pass): inverse row FFT, keep the first nx values scaled by `scale`, replace
+// each value u by a*u/|u| (a where u == 0) with a from amp ([ny][nx] float32), and, if
+// num is not null, store the row's FP64 sum of (|u| - a)^2 in num[row]. Then either
+// (out == nullptr) zero-pad and forward row FFT back into spec, or write the constrained
+// field to out ([ny][nx]).
+hipError_t launch_row_gs(float2* spec, const float* amp, float2* out, double* num, int nx, int ny,
+                         int mx, float scale, const float2* tw, hipStream_t s);
+// errors[k] = sqrt(sum_rows num[k*ny + row] / sum(amp^2)), k < iters; den_work holds 1 double.
+hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
+                            int nx, int ny, int iters, hipStream_t s);
+
 // Fresnel transfer-function factors of up to kZChunk planes that share the geometry:
 // plane k gets Hx_k = C_k * DFT_mx(hx_k) at out + k*(mx+my) and Hy_k = DFT_my(hy_k) right
 // after it, where h*_k are the sampled 1-D chirps exp(i pi (s(d) pitch)^2 / (lambda z_k)).

@@ -41,8 +41,9 @@ STAGE_COL = 1
 STAGE_ROW_INV = 2
 STAGE_TABLES = 3
 STAGE_COL_Z = 4
+STAGE_ROW_GS = 5
 STAGE_NAMES = {STAGE_ROW_FWD: "row_fwd", STAGE_COL: "col", STAGE_ROW_INV: "row_inv",
-               STAGE_TABLES: "tables", STAGE_COL_Z: "col_z"}
+               STAGE_TABLES: "tables", STAGE_COL_Z: "col_z", STAGE_ROW_GS: "row_gs"}
 KINDS = {"asm": ANGULAR, "angular": ANGULAR, "fresnel": FRESNEL_CONV}
 
 
@@ -83,6 +84,9 @@ SIGNATURES = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int32,
                                    ctypes.c_void_p]),
+    "cwo_gs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p]),
     "cwo_check_params": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.c_int32]),
     "cwo_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "cwo_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -237,6 +241,30 @@ class Context:
         if st != CWO_OK:
             raise CwoError(st, "cwo_zstack")
         return out
+
+    def gs(self, u, a1, a2, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, iterations=1,
+           errors=True, precision="f32", stream=None):
+        """Ping-pong iteration in place on u (complex64 [ny, nx]); a1, a2 float32 amplitude
+        targets at the two planes. Returns the float32 tensor of E_k (or None)."""
+        import torch
+        u = self._field(u)
+        ny, nx = u.shape
+        for a in (a1, a2):
+            if (not isinstance(a, torch.Tensor) or a.dtype != torch.float32 or a.shape != u.shape
+                    or not a.is_contiguous() or a.device != u.device):
+                raise ValueError("amplitude targets must be contiguous float32 [ny, nx] on the "
+                                 "field's device")
+        p = make_params(nx, ny, dx, dy, wavelength, z, ANGULAR, precision)
+        err = torch.empty(max(int(iterations), 1), dtype=torch.float32, device=u.device) \
+            if errors else None
+        st = self._lib.cwo_gs(self.handle, ctypes.byref(p), ctypes.c_void_p(a1.data_ptr()),
+                              ctypes.c_void_p(a2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                              int(iterations),
+                              ctypes.c_void_p(err.data_ptr() if err is not None else 0),
+                              self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_gs")
+        return err[:int(iterations)] if err is not None else None
 
     def batch(self, jobs, stream=None):
         """Run a list of (kind, u, out, dict(dx=, dy=, wavelength=, z=, ...)) jobs in order."""
