@@ -30,9 +30,9 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per launch of each kernel for an N x N field, M = 2N, complex64
 # intermediates: row_fwd reads the field and writes the N x M spectrum rows; col reads
 # and writes the N x M plane in place; row_inv reads it and writes the field.
-def stage_bytes(n: int) -> dict:
+def stage_bytes(n: int, elem: int = 8) -> dict:
     field = 8 * n * n
-    plane = 8 * n * (2 * n)
+    plane = elem * n * (2 * n)
     return {"row_fwd": field + plane, "col": 2 * plane, "row_inv": plane + field}
 
 
@@ -107,6 +107,8 @@ def main():
                     help="field size other than the headline 2048 (a side measurement)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the z-stack (batched form) measurements")
+    ap.add_argument("--precision", choices=["f32", "f16", "bf16"], default="f32",
+                    help="storage of the padded planes (arithmetic is always FP32)")
     ap.add_argument("--no-gs", action="store_true",
                     help="skip the ping-pong (GS) iteration measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -137,7 +139,7 @@ def main():
     prop = ctx.asm if args.kind == "asm" else ctx.fresnel
 
     def step():
-        prop(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=out)
+        prop(u, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=out, precision=args.precision)
 
     for _ in range(args.warmup):
         step()
@@ -162,7 +164,7 @@ def main():
     ms_per_step = total_ms / args.steps
     value = 1000.0 / ms_per_step
 
-    sb = stage_bytes(n)
+    sb = stage_bytes(n, 8 if args.precision == "f32" else 4)
     for name, rec in kernels.items():
         rec["alg_bytes"] = sb[name]
         rec["GBps"] = sb[name] / (rec["avg_us"] * 1e-6) / 1e9
@@ -176,7 +178,7 @@ def main():
                 "plane_GBps": round(sum(sb.values()) / (ms_per_step * 1e-3) / 1e9, 1)}
 
     batched = None
-    if not args.no_batched and args.kind == "asm":
+    if not args.no_batched and args.kind == "asm" and args.precision == "f32":
         # batched form: the same field to 64 distances in one cwo_zstack call, against the
         # same 64 distances as 64 plain calls (the plain figure above is one distance)
         zs = list(W.zstack_distances(64, 0.05, 0.5))
@@ -193,7 +195,7 @@ def main():
         del u3
 
     gs = None
-    if not args.no_gs and args.kind == "asm" and n == cfg.n:
+    if not args.no_gs and args.kind == "asm" and n == cfg.n and args.precision == "f32":
         # 200 ping-pong iterations (400 propagations) between two 2048^2 planes 0.1 m apart
         a1, a2, u0 = W.gs_problem(2048)
         ta1 = torch.from_numpy(a1).to(dev)
@@ -228,7 +230,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "f32" else "f32 (%s storage)" % args.precision,
         "data": "synthetic",
         "config": {"workload": "%s-%d: %dx%d complex64 rectangles+random phase, pitch 8um, "
                                "532nm, z=0.5m, padded to %dx%d, plain per-call form"

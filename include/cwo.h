@@ -46,7 +46,8 @@ typedef enum {
     CWO_ERR_INVALID = -1,     /* null pointer, non-finite or non-positive pitch/wavelength,
                                  non-finite z, Fresnel with z == 0, unknown kind/flag,
                                  bad count */
-    CWO_ERR_UNSUPPORTED = -2, /* size not a power of two in [16, 4096], precision not built */
+    CWO_ERR_UNSUPPORTED = -2, /* size not a power of two in [16, 4096], precision not built
+                                 for this call */
     CWO_ERR_NOMEM = -3,       /* device allocation failed, or a job larger than the budget */
     CWO_ERR_DEVICE = -4,      /* a HIP call failed; sticky on the context */
     CWO_ERR_NOTFOUND = -5     /* unknown ticket */
@@ -55,8 +56,13 @@ typedef enum {
 /* Diffraction kinds (the paper's CWO_ANGULAR and CWO_FRESNEL_CONV selectors). */
 typedef enum { CWO_ANGULAR = 1, CWO_FRESNEL_CONV = 2 } cwo_kind;
 
-/* Storage precision of the padded intermediate planes; butterflies are always FP32 and
- * the field in/out is always complex64. */
+/* Storage precision of the padded intermediate planes; butterflies and the transfer
+ * function are always FP32 (phase reduction FP64) and the field in/out is always
+ * complex64. FP16/BF16 store each complex as two 16-bit values (round to nearest even);
+ * FP16 also scales the field by 2^-e (e = binary exponent of its largest component, found
+ * on the device) and every transform by a power of two, undone exactly at the output.
+ * Built for cwo_asm / cwo_fresnel (and single jobs of cwo_batch) in padded mode;
+ * elsewhere CWO_ERR_UNSUPPORTED. */
 typedef enum { CWO_PREC_F32 = 0, CWO_PREC_F16_STORAGE = 1, CWO_PREC_BF16_STORAGE = 2 } cwo_precision;
 
 /* Flags. CWO_FLAG_NOPAD keeps M = N (circular convolution without padding); it exists for

@@ -54,6 +54,7 @@ struct cwo_ctx {
     Buffer fwork;                     // FP64 chirps and twiddles for the Fresnel factors
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     Buffer gsnum;                     // per-row error partials of the ping-pong iteration
+    Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
     std::list<FresnelEntry> fresnel;  // most recently used first
     // per-kernel timing
     bool profiling = false;
@@ -143,7 +144,7 @@ const float2* twiddle_table(cwo_ctx* c, int m, hipStream_t s, cwo_status* st) {
 }
 
 size_t held_bytes(const cwo_ctx* c) {
-    return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes + c->gsnum.bytes;
+    return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes + c->gsnum.bytes + c->rwork.bytes;
 }
 
 void* ensure(cwo_ctx* c, Buffer& b, size_t bytes, cwo_status* st) {
@@ -172,8 +173,9 @@ void* ensure(cwo_ctx* c, Buffer& b, size_t bytes, cwo_status* st) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Everything except the distance.
-cwo_status validate_geometry(const cwo_params* p, int kind) {
+// Everything except the distance. low_prec: FP16/BF16 storage is built for this call
+// (single padded propagations); elsewhere it is CWO_ERR_UNSUPPORTED.
+cwo_status validate_geometry(const cwo_params* p, int kind, bool low_prec = false) {
     if (!p) return CWO_ERR_INVALID;
     if (kind != CWO_ANGULAR && kind != CWO_FRESNEL_CONV) return CWO_ERR_INVALID;
     if (p->kind != 0 && p->kind != kind) return CWO_ERR_INVALID;
@@ -183,7 +185,8 @@ cwo_status validate_geometry(const cwo_params* p, int kind) {
     if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
         p->ny > kMaxN)
         return CWO_ERR_UNSUPPORTED;
-    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    if (p->precision != CWO_PREC_F32 && (!low_prec || (p->flags & CWO_FLAG_NOPAD)))
+        return CWO_ERR_UNSUPPORTED;
     return CWO_OK;
 }
 
@@ -193,8 +196,8 @@ cwo_status validate_z(double z, int kind) {
     return CWO_OK;
 }
 
-cwo_status validate(const cwo_params* p, int kind) {
-    cwo_status st = validate_geometry(p, kind);
+cwo_status validate(const cwo_params* p, int kind, bool low_prec = false) {
+    cwo_status st = validate_geometry(p, kind, low_prec);
     if (st != CWO_OK) return st;
     return validate_z(p->z, kind);
 }
@@ -206,6 +209,14 @@ struct Geometry {
 Geometry geometry(const cwo_params* p) {
     const bool nopad = (p->flags & CWO_FLAG_NOPAD) != 0;
     return Geometry{p->nx, p->ny, nopad ? p->nx : 2 * p->nx, nopad ? p->ny : 2 * p->ny};
+}
+
+size_t elem_bytes(int precision) { return precision == CWO_PREC_F32 ? 8 : 4; }
+
+int ilog2(int v) {
+    int e = 0;
+    while ((1 << (e + 1)) <= v) ++e;
+    return e;
 }
 
 cwo::AsmScalars asm_scalars(const cwo_params* p, const Geometry& g, double z) {
@@ -299,7 +310,7 @@ cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const voi
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    float2* buf = (float2*)ensure(c, c->scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    void* buf = ensure(c, c->scratch, elem_bytes(p->precision) * (size_t)g.ny * g.mx, &st);
     if (!buf) return st;
     const float2* fin = (const float2*)in;
     float2* fout = (float2*)out;
@@ -308,22 +319,41 @@ cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const voi
         h = fresnel_factors(c, p, g, s, &st);
         if (!h) return st;
     }
+    cwo::Storage sto;  // complex64: no intermediate scaling, 1/(Mx My) at the end
+    sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);  // power of two: exact
+    if (p->precision != CWO_PREC_F32) {
+        // FP16/BF16 storage: 2^-floor(log2(Mx)/2) before the row transform, 1/My in the
+        // column pass, the rest of 1/Mx at the end (all powers of two); FP16 also scales
+        // the field by 2^-e, e the exponent of its largest component, found on the device
+        sto.prec = p->precision == CWO_PREC_F16_STORAGE ? 1 : 2;
+        const int kx = ilog2(g.mx) / 2;
+        sto.in_scale = std::ldexp(1.0f, -kx);
+        sto.col_scale = 1.0f / (float)g.my;
+        sto.out_scale = std::ldexp(1.0f, kx) / (float)g.mx;
+        if (sto.prec == 1) {
+            float* rw = (float*)ensure(c, c->rwork, sizeof(float) * (2 + cwo::kRangeBlocks), &st);
+            if (!rw) return st;
+            CWO_HIP(c, cwo::launch_range_scale(fin, (size_t)g.ny * g.nx, rw, s));
+            sto.dyn_scale = rw;
+            sto.dyn_inv = rw + 1;
+        }
+    }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
-                return cwo::launch_row_fwd(fin, buf, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
+                return cwo::launch_row_fwd(fin, buf, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s);
             }));
     if (kind == CWO_ANGULAR) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, twy, s);
+                    return cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, sto, twy, s);
                 }));
     } else {
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, 1, 0, h, h + g.mx, twy, s);
+                    return cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, 1, 0, h, h + g.mx, sto, twy,
+                                                   s);
                 }));
     }
-    const float scale = 1.0f / ((float)g.mx * (float)g.my);  // power of two: exact
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
-                return cwo::launch_row_inv(buf, fout, g.nx, g.ny, g.mx, 1, 0, 0, scale, twx, s);
+                return cwo::launch_row_inv(buf, fout, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s);
             }));
     return CWO_OK;
 }
@@ -331,7 +361,7 @@ cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const voi
 cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
                      void* stream) {
     if (!c) return CWO_ERR_INVALID;
-    cwo_status st = validate(p, kind);
+    cwo_status st = validate(p, kind, true);
     if (st != CWO_OK) return st;
     if (!in || !out) return CWO_ERR_INVALID;
     std::lock_guard<std::mutex> lock(c->mu);
@@ -442,7 +472,7 @@ cwo_status cwo_destroy(cwo_ctx* c) {
         (void)drain_profile(c);
         for (auto& kv : c->twiddles) (void)hipFree(kv.second);
         for (auto& e : c->fresnel) (void)hipFree(e.h);
-        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab, &c->gsnum})
+        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab, &c->gsnum, &c->rwork})
             if (b->p) (void)hipFree(b->p);
         for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
     }
@@ -478,7 +508,9 @@ cwo_status cwo_batch(cwo_ctx* c, const cwo_job* jobs, int32_t njobs, void* strea
     if (!c || (!jobs && njobs > 0) || njobs < 0) return CWO_ERR_INVALID;
     cwo_status st;
     for (int i = 0; i < njobs; ++i) {
-        if ((st = validate(&jobs[i].p, jobs[i].p.kind)) != CWO_OK) return st;
+        const bool grouped = (i > 0 && same_group(jobs[i - 1], jobs[i])) ||
+                             (i + 1 < njobs && same_group(jobs[i], jobs[i + 1]));
+        if ((st = validate(&jobs[i].p, jobs[i].p.kind, !grouped)) != CWO_OK) return st;
         if (!jobs[i].in || !jobs[i].out) return CWO_ERR_INVALID;
     }
     std::lock_guard<std::mutex> lock(c->mu);
@@ -580,14 +612,14 @@ cwo_status cwo_profile_read(cwo_ctx* c, int32_t stage, double* total_ms, int64_t
     return CWO_OK;
 }
 
-cwo_status cwo_check_params(const cwo_params* p, int32_t kind) { return validate(p, kind); }
+cwo_status cwo_check_params(const cwo_params* p, int32_t kind) { return validate(p, kind, true); }
 
 size_t cwo_scratch_bytes(const cwo_params* p) {
     if (!p) return 0;
     const int kind = p->kind == 0 ? CWO_ANGULAR : p->kind;
-    if (validate(p, kind) != CWO_OK) return 0;
+    if (validate(p, kind, true) != CWO_OK) return 0;
     const Geometry g = geometry(p);
-    return sizeof(float2) * (size_t)g.ny * (size_t)g.mx;
+    return elem_bytes(p->precision) * (size_t)g.ny * (size_t)g.mx;
 }
 
 const char* cwo_strerror(cwo_status s) {

@@ -21,6 +21,36 @@ namespace cwo {
 constexpr int FWD = -1;
 constexpr int INV = +1;
 
+// ---- storage of the padded intermediate planes --------------------------------
+// complex64 (FP32), or two FP16 / two BF16 values per complex (rounded to nearest
+// even on the way in). Arithmetic is always FP32.
+struct StF32 {
+    using E = float2;
+    __device__ __forceinline__ static float2 dec(E v) { return v; }
+    __device__ __forceinline__ static E enc(float2 v) { return v; }
+};
+struct alignas(4) half2s {
+    _Float16 x, y;
+};
+struct StF16 {
+    using E = half2s;
+    __device__ __forceinline__ static float2 dec(E v) { return make_float2((float)v.x, (float)v.y); }
+    __device__ __forceinline__ static E enc(float2 v) { return E{(_Float16)v.x, (_Float16)v.y}; }
+};
+struct alignas(4) bf162s {
+    __bf16 x, y;
+};
+struct StBF16 {
+    using E = bf162s;
+    __device__ __forceinline__ static float2 dec(E v) { return make_float2((float)v.x, (float)v.y); }
+    __device__ __forceinline__ static E enc(float2 v) { return E{(__bf16)v.x, (__bf16)v.y}; }
+};
+// P adjacent stored elements, loaded and stored as one vector access
+template <class E, int P>
+struct alignas(sizeof(E) * P) Pack {
+    E e[P];
+};
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "fft_device.hpp"
@@ -90,14 +91,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 
 // ---- row forward: zero-pad + FFT --------------------------------------------
 
-template <int M, bool HALF>
+// Scaling of the stored planes (powers of two, exact): the field is multiplied by
+// sc.in * (*sc.dyn) before the row transform (sc.dyn: a device-computed factor or null).
+struct RowScale {
+    float in;
+    const float* dyn;
+};
+
+template <int M, bool HALF, class ST>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __restrict__ in,
-                                                                  float2* __restrict__ out, int nx,
-                                                                  int ny, size_t in_plane,
-                                                                  size_t out_plane,
+                                                                  typename ST::E* __restrict__ out,
+                                                                  int nx, int ny, size_t in_plane,
+                                                                  size_t out_plane, RowScale sc,
                                                                   const float2* __restrict__ tw) {
     using C = RowCfg<M>;
     constexpr int E = C::E, T = C::T;
+    const float f = sc.dyn ? sc.in * *sc.dyn : sc.in;
     __shared__ float2 lds[C::RPB * lds_elems<M>()];
     const int tid = threadIdx.x;
     const int sub = tid / T, j = tid % T;
@@ -115,11 +124,15 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
             v[0][r] = (valid && x < nx) ? src[x] : make_float2(0.f, 0.f);
         }
     }
+    if (f != 1.0f) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[0][r] = make_float2(v[0][r].x * f, v[0][r].y * f);
+    }
     fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
-        float2* dst = out + blockIdx.y * out_plane + (size_t)row * M;
+        typename ST::E* dst = out + blockIdx.y * out_plane + (size_t)row * M;
 #pragma unroll
-        for (int r = 0; r < E; ++r) dst[j + r * T] = v[0][r];
+        for (int r = 0; r < E; ++r) dst[j + r * T] = ST::enc(v[0][r]);
     }
 }
 
@@ -224,12 +237,15 @@ struct FresnelH {
     }
 };
 
-template <int M, bool HALF, class HF>
-__global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__ buf, int ny,
-                                                              int mx, size_t plane, HF hf,
+template <int M, bool HALF, class HF, class ST>
+__global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(typename ST::E* __restrict__ buf,
+                                                              int ny, int mx, size_t plane, HF hf,
+                                                              float hscale,
                                                               const float2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int E = C::E, T = C::T, P = C::P;
+    using SE = typename ST::E;
+    using PK = Pack<SE, P>;
     __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
     float2* lds = reinterpret_cast<float2*>(lds4);
     const int tid = threadIdx.x;
@@ -238,19 +254,19 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__
     const int col0 = (blk * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
     const bool active = col0 < mx;                 // blocks may overhang narrow planes
     const int col = active ? col0 : 0;
-    float2* base = buf + blockIdx.y * plane + col;
+    SE* base = buf + blockIdx.y * plane + col;
     float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
         const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
-        if constexpr (P == 2) {
-            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (ld) t = *reinterpret_cast<const float4*>(base + (size_t)y * mx);
-            v[0][r] = make_float2(t.x, t.y);
-            v[1][r] = make_float2(t.z, t.w);
+        if (ld) {
+            const PK t = *reinterpret_cast<const PK*>(base + (size_t)y * mx);
+#pragma unroll
+            for (int p = 0; p < P; ++p) v[p][r] = ST::dec(t.e[p]);
         } else {
-            v[0][r] = ld ? base[(size_t)y * mx] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int p = 0; p < P; ++p) v[p][r] = make_float2(0.f, 0.f);
         }
     }
     float2* my_lds = lds + pair * C::LDS_PAIR;
@@ -262,7 +278,11 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__
     for (int r = 0; r < E; ++r) {
         const typename HF::Row hr = hf.row(j + r * T);
 #pragma unroll
-        for (int p = 0; p < P; ++p) v[p][r] = cmul(v[p][r], hf(hc[p], hr));
+        for (int p = 0; p < P; ++p) {
+            float2 h = hf(hc[p], hr);
+            if (hscale != 1.0f) h = make_float2(h.x * hscale, h.y * hscale);
+            v[p][r] = cmul(v[p][r], h);
+        }
     }
     fft<M, E, P, INV>(v, my_lds, j, tw);
 #pragma unroll
@@ -270,11 +290,10 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(float2* __restrict__
         const int y = j + r * T;
         const bool st = active && (HALF ? (r < E / 2) : (y < ny));
         if (st) {
-            if constexpr (P == 2)
-                *reinterpret_cast<float4*>(base + (size_t)y * mx) =
-                    make_float4(v[0][r].x, v[0][r].y, v[1][r].x, v[1][r].y);
-            else
-                base[(size_t)y * mx] = v[0][r];
+            PK t;
+#pragma unroll
+            for (int p = 0; p < P; ++p) t.e[p] = ST::enc(v[p][r]);
+            *reinterpret_cast<PK*>(base + (size_t)y * mx) = t;
         }
     }
 }
@@ -451,22 +470,22 @@ struct OutTable {
     __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
 };
 
-template <int M, bool HALF, class OUT>
-__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(const float2* __restrict__ in,
-                                                                  OUT outs, int nx, int ny,
-                                                                  size_t in_plane, float scale,
-                                                                  const float2* __restrict__ tw) {
+template <int M, bool HALF, class OUT, class ST>
+__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
+    const typename ST::E* __restrict__ in, OUT outs, int nx, int ny, size_t in_plane, float scale,
+    const float* __restrict__ dyn_inv, const float2* __restrict__ tw) {
     using C = RowCfg<M>;
     constexpr int E = C::E, T = C::T;
+    if (dyn_inv) scale *= *dyn_inv;
     __shared__ float2 lds[C::RPB * lds_elems<M>()];
     const int tid = threadIdx.x;
     const int sub = tid / T, j = tid % T;
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
-    const float2* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * M;
+    const typename ST::E* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * M;
     float2 v[1][E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[0][r] = valid ? src[j + r * T] : make_float2(0.f, 0.f);
+    for (int r = 0; r < E; ++r) v[0][r] = valid ? ST::dec(src[j + r * T]) : make_float2(0.f, 0.f);
     fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
         float2* dst = outs(blockIdx.y) + (size_t)row * nx;
@@ -705,41 +724,79 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
-                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s) {
+template <class ST>
+static hipError_t launch_row_fwd_t(const float2* in, void* out, int nx, int ny, int mx, int batch,
+                                   size_t in_plane, size_t out_plane, RowScale sc,
+                                   const float2* tw, hipStream_t s) {
     const bool half = (mx == 2 * nx);
+    using SE = typename ST::E;
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
         if (half)
-            hipLaunchKernelGGL((k_row_fwd<MM, true>), grid, dim3(C::THREADS), 0, s, in, out, nx, ny,
-                               in_plane, out_plane, tw);
+            hipLaunchKernelGGL((k_row_fwd<MM, true, ST>), grid, dim3(C::THREADS), 0, s, in,
+                               (SE*)out, nx, ny, in_plane, out_plane, sc, tw);
+        else if constexpr (std::is_same_v<ST, StF32>)
+            hipLaunchKernelGGL((k_row_fwd<MM, false, ST>), grid, dim3(C::THREADS), 0, s, in,
+                               (SE*)out, nx, ny, in_plane, out_plane, sc, tw);
         else
-            hipLaunchKernelGGL((k_row_fwd<MM, false>), grid, dim3(C::THREADS), 0, s, in, out, nx,
-                               ny, in_plane, out_plane, tw);
+            return hipErrorInvalidValue;
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
+                          hipStream_t s) {
+    const RowScale sc{st.in_scale, st.dyn_scale};
+    switch (st.prec) {
+        case 0: return launch_row_fwd_t<StF32>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
+        case 1: return launch_row_fwd_t<StF16>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
+        case 2: return launch_row_fwd_t<StBF16>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s) {
+    return launch_row_fwd_t<StF32>(in, out, nx, ny, mx, batch, in_plane, out_plane,
+                                   RowScale{1.0f, nullptr}, tw, s);
+}
+
+template <class HF, class ST>
+static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                               const HF& hf, float hscale, const float2* tw, hipStream_t s) {
+    const bool half = (my == 2 * ny);
+    using SE = typename ST::E;
+    CWO_DISPATCH_M(my, {
+        using C = ColCfg<MM>;
+        dim3 grid((mx + C::COLS - 1) / C::COLS, batch);
+        if (half)
+            hipLaunchKernelGGL((k_col<MM, true, HF, ST>), grid, dim3(C::THREADS), 0, s, (SE*)buf,
+                               ny, mx, plane, hf, hscale, tw);
+        else if constexpr (std::is_same_v<ST, StF32>)
+            hipLaunchKernelGGL((k_col<MM, false, HF, ST>), grid, dim3(C::THREADS), 0, s, (SE*)buf,
+                               ny, mx, plane, hf, hscale, tw);
+        else
+            return hipErrorInvalidValue;
     });
     return hipGetLastError();
 }
 
 template <class HF>
-static hipError_t launch_col_impl(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                                  const HF& hf, const float2* tw, hipStream_t s) {
-    const bool half = (my == 2 * ny);
-    CWO_DISPATCH_M(my, {
-        using C = ColCfg<MM>;
-        dim3 grid((mx + C::COLS - 1) / C::COLS, batch);
-        if (half)
-            hipLaunchKernelGGL((k_col<MM, true, HF>), grid, dim3(C::THREADS), 0, s, buf, ny, mx,
-                               plane, hf, tw);
-        else
-            hipLaunchKernelGGL((k_col<MM, false, HF>), grid, dim3(C::THREADS), 0, s, buf, ny, mx,
-                               plane, hf, tw);
-    });
-    return hipGetLastError();
+static hipError_t launch_col_impl(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                                  const HF& hf, const Storage& st, const float2* tw,
+                                  hipStream_t s) {
+    switch (st.prec) {
+        case 0: return launch_col_t<HF, StF32>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
+        case 1: return launch_col_t<HF, StF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
+        case 2: return launch_col_t<HF, StBF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                          const AsmScalars& a, const float2* tw, hipStream_t s) {
+hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                          const AsmScalars& a, const Storage& st, const float2* tw, hipStream_t s) {
     // largest s = (lambda fx)^2 + (lambda fy)^2 on the grid: the Nyquist corner
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
     const double smax = sx * sx + sy * sy;
@@ -752,34 +809,51 @@ hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t
         hf.c0 = (float)(a.zl - std::nearbyint(a.zl));
         hf.mx = mx;
         hf.my = my;
-        return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
+        return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
     }
     AsmH hf{a.dfx, a.dfy, a.lam, a.zl, mx, my};
-    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
+    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
 }
 
-hipError_t launch_col_fresnel(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                              const float2* hx, const float2* hy, const float2* tw, hipStream_t s) {
+hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
+                          const AsmScalars& a, const float2* tw, hipStream_t s) {
+    return launch_col_asm((void*)buf, ny, my, mx, batch, plane, a, Storage{}, tw, s);
+}
+
+hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                              const float2* hx, const float2* hy, const Storage& st,
+                              const float2* tw, hipStream_t s) {
     FresnelH hf{hx, hy};
-    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, tw, s);
+    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
+}
+
+template <class OUT, class ST>
+static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int ny, int mx,
+                                   int batch, size_t in_plane, float scale, const float* dyn_inv,
+                                   const float2* tw, hipStream_t s) {
+    const bool half = (mx == 2 * nx);
+    using SE = typename ST::E;
+    CWO_DISPATCH_M(mx, {
+        using C = RowCfg<MM>;
+        dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
+        if (half)
+            hipLaunchKernelGGL((k_row_inv<MM, true, OUT, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)in, outs, nx, ny, in_plane, scale, dyn_inv, tw);
+        else if constexpr (std::is_same_v<ST, StF32>)
+            hipLaunchKernelGGL((k_row_inv<MM, false, OUT, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)in, outs, nx, ny, in_plane, scale, dyn_inv, tw);
+        else
+            return hipErrorInvalidValue;
+    });
+    return hipGetLastError();
 }
 
 template <class OUT>
 static hipError_t launch_row_inv_impl(const float2* in, const OUT& outs, int nx, int ny, int mx,
                                       int batch, size_t in_plane, float scale, const float2* tw,
                                       hipStream_t s) {
-    const bool half = (mx == 2 * nx);
-    CWO_DISPATCH_M(mx, {
-        using C = RowCfg<MM>;
-        dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
-        if (half)
-            hipLaunchKernelGGL((k_row_inv<MM, true, OUT>), grid, dim3(C::THREADS), 0, s, in, outs,
-                               nx, ny, in_plane, scale, tw);
-        else
-            hipLaunchKernelGGL((k_row_inv<MM, false, OUT>), grid, dim3(C::THREADS), 0, s, in, outs,
-                               nx, ny, in_plane, scale, tw);
-    });
-    return hipGetLastError();
+    return launch_row_inv_t<OUT, StF32>(in, outs, nx, ny, mx, batch, in_plane, scale, nullptr, tw,
+                                        s);
 }
 
 hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx, int batch,
@@ -787,6 +861,79 @@ hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx,
                           hipStream_t s) {
     return launch_row_inv_impl(in, OutStrided{out, out_plane}, nx, ny, mx, batch, in_plane, scale,
                                tw, s);
+}
+
+hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
+                          hipStream_t s) {
+    const OutStrided o{out, out_plane};
+    switch (st.prec) {
+        case 0:
+            return launch_row_inv_t<OutStrided, StF32>(in, o, nx, ny, mx, batch, in_plane,
+                                                       st.out_scale, st.dyn_inv, tw, s);
+        case 1:
+            return launch_row_inv_t<OutStrided, StF16>(in, o, nx, ny, mx, batch, in_plane,
+                                                       st.out_scale, st.dyn_inv, tw, s);
+        case 2:
+            return launch_row_inv_t<OutStrided, StBF16>(in, o, nx, ny, mx, batch, in_plane,
+                                                        st.out_scale, st.dyn_inv, tw, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---- range of a field for FP16 storage -----------------------------------------
+
+// per-block maximum of |re|, |im| over a grid-strided range
+__global__ __launch_bounds__(256) void k_absmax_partial(const float2* __restrict__ in, size_t n,
+                                                        float* __restrict__ partial) {
+    __shared__ float red[256];
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 v = in[i];
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// scale[0] = 2^-e with e = ceil(log2(max)) (so the scaled field is within [-1, 1]),
+// scale[1] = 2^e; both 1 when the field is zero or not finite
+__global__ __launch_bounds__(256) void k_absmax_final(const float* __restrict__ partial, int np,
+                                                      float* __restrict__ scale) {
+    __shared__ float red[256];
+    float m = 0.f;
+    for (int i = threadIdx.x; i < np; i += 256) m = fmaxf(m, partial[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float mx = red[0];
+        int e = 0;
+        if (mx > 0.f && isfinite(mx)) {
+            const float f = frexpf(mx, &e);  // mx = f * 2^e, f in [0.5, 1)
+            (void)f;
+        }
+        scale[0] = ldexpf(1.0f, -e);
+        scale[1] = ldexpf(1.0f, e);
+    }
+}
+
+hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream_t s) {
+    const int blocks = (int)((n + 256 * 16 - 1) / (256 * 16)) < kRangeBlocks
+                           ? (int)((n + 256 * 16 - 1) / (256 * 16))
+                           : kRangeBlocks;
+    const int nb = blocks < 1 ? 1 : blocks;
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, s, in, n, work + 2);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, (const float*)(work + 2), nb, work);
+    return hipGetLastError();
 }
 
 hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,

@@ -28,7 +28,37 @@ struct ZChunk {
     float2* out[kZChunk];    // destination field of each plane, [ny][nx]
 };
 
+// Storage of the padded planes and the power-of-two scalings that keep FP16 in range:
+// the field is multiplied by in_scale * (*dyn_scale) before the row transform, the
+// transfer function by col_scale, and the output by out_scale * (*dyn_inv).
+struct Storage {
+    int prec = 0;            // 0 complex64, 1 FP16 pairs, 2 BF16 pairs
+    float in_scale = 1.0f;
+    const float* dyn_scale = nullptr;
+    float col_scale = 1.0f;
+    float out_scale = 1.0f;
+    const float* dyn_inv = nullptr;
+};
+
+constexpr int kRangeBlocks = 1024;
+// work[0] = 2^-e, work[1] = 2^e with e = the binary exponent of max(|re|, |im|) over the
+// n values; work must hold 2 + kRangeBlocks floats.
+hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream_t s);
+
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s);
+
+// precision-generic forms (padded planes only for FP16/BF16)
+hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
+                          hipStream_t s);
+hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                          const AsmScalars& a, const Storage& st, const float2* tw, hipStream_t s);
+hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
+                              const float2* hx, const float2* hy, const Storage& st,
+                              const float2* tw, hipStream_t s);
+hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,
+                          size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
+                          hipStream_t s);
 
 // in: batch planes of [ny][nx] (plane stride in_plane elements); out: [ny][mx] per plane
 hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
@@ -37,8 +67,7 @@ hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx,
 // buf: batch planes of [ny][mx], column transform of length my (my = ny or 2*ny)
 hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
                           const AsmScalars& a, const float2* tw, hipStream_t s);
-hipError_t launch_col_fresnel(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                              const float2* hx, const float2* hy, const float2* tw, hipStream_t s);
+
 
 // in: [ny][mx] per plane; out: [ny][nx] per plane, scaled by `scale`
 hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx, int batch,

@@ -100,3 +100,13 @@ def test_null_context_and_pointers_are_invalid():
     assert lib.cwo_asm(None, ctypes.byref(p), None, None, None) == cwo.CWO_ERR_INVALID
     assert lib.cwo_destroy(None) == cwo.CWO_ERR_INVALID
     assert lib.cwo_create(None, 0, 0) == cwo.CWO_ERR_INVALID
+
+
+def test_low_precision_storage_params():
+    for prec in (cwo.PREC_F16, cwo.PREC_BF16):
+        p = cwo.make_params(256, 256, 10e-6, z=0.1, precision=prec)
+        assert cwo.check_params(p, cwo.ANGULAR) == cwo.CWO_OK
+        assert cwo.check_params(p, cwo.FRESNEL_CONV) == cwo.CWO_OK
+        assert cwo.load().cwo_scratch_bytes(ctypes.byref(p)) == 4 * 256 * 512
+        p = cwo.make_params(256, 256, 10e-6, z=0.1, precision=prec, nopad=True)
+        assert cwo.check_params(p, cwo.ANGULAR) == cwo.CWO_ERR_UNSUPPORTED

@@ -1,0 +1,84 @@
+"""GPU parity of FP16 / BF16 storage of the padded intermediate planes.
+
+Butterflies, transfer function and accumulation stay FP32; only the two stored
+planes are rounded to 16-bit (round to nearest even). The bound is relative L2
+<= 3e-3 against the FP64 oracle. Expected: FP16 (11-bit significand, RMS rounding
+error ~1.4e-4 per stored value, two stores) ~3e-4; BF16 (8-bit, ~1.1e-3 per store)
+~1.6e-3. The FP32 path is also run to show the bound is not met trivially.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1107_5578_amd import cwo
+    c = cwo.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def run(ctx, kind, u, dx, lam, z, precision):
+    import torch
+    note("%s %s n=%s precision=%s" % (kind, "", u.shape, precision))
+    t = torch.from_numpy(u).cuda()
+    fn = ctx.asm if kind == D.ASM else ctx.fresnel
+    y = fn(t, dx, dx, lam, z, precision=precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", [D.ASM, D.FRESNEL])
+def test_plane_2048_low_precision(ctx, kind):
+    cfg = W.PLANE_2048
+    u = W.field_for(cfg)
+    ref = D.propagate(u, kind, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+    for prec, bound, expect in (("f16", 3e-3, 1e-3), ("bf16", 3e-3, 3e-3)):
+        y = run(ctx, kind, u, cfg.pitch, cfg.wavelength, cfg.z, prec)
+        rl = D.rel_l2(y, ref)
+        note("%s-2048 %s rel_l2=%.3e" % (kind, prec, rl))
+        assert np.all(np.isfinite(y))
+        assert rl <= bound
+        assert rl <= expect
+
+
+@pytest.mark.parametrize("n,ny", [(256, 256), (512, 128), (16, 64), (4096, 4096)])
+def test_sizes_f16(ctx, n, ny):
+    u = W.uniform_random_field(n, 900 + n, ny=ny)
+    # a large dynamic range: scale the field so FP16 without range scaling would overflow
+    u = (u * np.float32(3e4)).astype(np.complex64)
+    ref = D.asm(u, 8e-6, 8e-6, 532e-9, 0.2)
+    y = run(ctx, D.ASM, u, 8e-6, 532e-9, 0.2, "f16")
+    rl = D.rel_l2(y, ref)
+    note("asm-%dx%d f16 x3e4 rel_l2=%.3e" % (n, ny, rl))
+    assert np.all(np.isfinite(y)) and rl <= 3e-3
+
+
+def test_tiny_field_f16(ctx):
+    u = (W.uniform_random_field(128, 5) * np.float32(1e-30)).astype(np.complex64)
+    ref = D.fresnel(u, 10e-6, 10e-6, 633e-9, 0.1)
+    y = run(ctx, D.FRESNEL, u, 10e-6, 633e-9, 0.1, "f16")
+    rl = D.rel_l2(y, ref)
+    note("fresnel-128 f16 x1e-30 rel_l2=%.3e" % rl)
+    assert rl <= 3e-3
+
+
+def test_zero_field_f16(ctx):
+    u = np.zeros((64, 64), dtype=np.complex64)
+    y = run(ctx, D.ASM, u, 10e-6, 633e-9, 0.1, "f16")
+    assert np.all(y == 0)
