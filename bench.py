@@ -95,6 +95,78 @@ def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm):
     return len(zs) * 1000.0 / ms, ms
 
 
+def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 0.95)):
+    """Serving: a stream of mixed requests (sizes 512..4096^2, ASM/Fresnel 50/50,
+    z ~ U[0.01, 1] m, wavelength in {473, 532, 633} nm, 8 um pitch) through cwo_submit /
+    cwo_poll under an HBM budget. Field content does not change the work, so each size uses
+    one seeded field; outputs rotate through a ring per size (a buffer is reused only after
+    its previous request is done)."""
+    import numpy as np
+    reqs = W.serving_requests(count, 1.0, seed=5)
+    sizes = sorted({r.n for r in reqs})
+    fields = {n: torch.from_numpy(W.uniform_random_field(n, 5000 + n)).to(dev) for n in sizes}
+    ring = 40
+    outs = {n: [torch.empty_like(fields[n]) for _ in range(ring)] for n in sizes}
+
+    def run(arrivals):
+        srv = ctx_cls(0, hbm_budget_bytes=budget)
+        owner = {n: [None] * ring for n in sizes}
+        used = {n: 0 for n in sizes}
+        tickets = []
+        t0 = time.perf_counter()
+        for r, ta in zip(reqs, arrivals):
+            if ta is not None:
+                while time.perf_counter() - t0 < ta:
+                    pass
+            k = used[r.n] % ring
+            used[r.n] += 1
+            prev = owner[r.n][k]
+            while prev is not None and srv.poll(prev) < 2:
+                time.sleep(0.0001)
+            t = srv.submit(r.kind, fields[r.n], outs[r.n][k], dx=r.pitch, wavelength=r.wavelength,
+                           z=r.z)
+            owner[r.n][k] = t
+            tickets.append(t)
+        srv.drain()
+        infos = [srv.info(t) for t in tickets]
+        srv.close()
+        lat = np.array([i["t_done"] - i["t_submit"] for i in infos]) * 1e3
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        return {"requests": len(infos), "req_per_s": round(len(infos) / span, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3)}
+
+    # plain per-call form on one stream, same requests in order (first 2000)
+    plain_ctx = ctx_cls(0)
+    nplain = min(2000, count)
+    for r in reqs[:8]:
+        (plain_ctx.asm if r.kind == "asm" else plain_ctx.fresnel)(
+            fields[r.n], r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs[:nplain]:
+        (plain_ctx.asm if r.kind == "asm" else plain_ctx.fresnel)(
+            fields[r.n], r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
+    torch.cuda.synchronize()
+    plain_rps = nplain / (time.perf_counter() - t0)
+    plain_ctx.close()
+
+    closed = run([None] * count)
+    cap = closed["req_per_s"]
+    out = {"workload": "%d requests, sizes %s^2 uniform, ASM/Fresnel 50/50, z~U[0.01,1] m, "
+                       "lambda in {473,532,633} nm, 8 um, HBM budget %d GiB"
+                       % (count, "/".join(str(n) for n in sizes), budget >> 30),
+           "plain_per_call_req_per_s": round(plain_rps, 1),
+           "closed_loop": closed, "served_vs_plain": round(cap / plain_rps, 3), "open_loop": {}}
+    for f in rates:
+        rng = np.random.default_rng(5)
+        gaps = rng.exponential(1.0 / (f * cap), size=count)
+        arr = list(np.cumsum(gaps) - gaps[0])
+        out["open_loop"]["%.2f" % f] = dict(run(arr), offered_req_per_s=round(f * cap, 1))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +181,8 @@ def main():
                     help="skip the z-stack (batched form) measurements")
     ap.add_argument("--precision", choices=["f32", "f16", "bf16"], default="f32",
                     help="storage of the padded planes (arithmetic is always FP32)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--no-gs", action="store_true",
                     help="skip the ping-pong (GS) iteration measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -218,6 +292,10 @@ def main():
               "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
         del ta1, ta2, tu
 
+    serve = None
+    if args.serve_requests > 0 and args.kind == "asm" and n == cfg.n and args.precision == "f32":
+        serve = serve_bench(cwo.Context, torch, W, dev, args.serve_requests)
+
     y = out.cpu().numpy()
     line = {
         "metric": "%s planes/s at %d^2 fp32 (plain per-call form)" % (args.kind.upper(), n),
@@ -245,6 +323,8 @@ def main():
         line["batched"] = batched
     if gs is not None:
         line["gs_pingpong"] = gs
+    if serve is not None:
+        line["serving"] = serve
     if not args.no_cpu_baseline:
         ref, base = cpu_baseline(u_np, cfg, args.kind)
         from oracle import diffraction as D

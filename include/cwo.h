@@ -95,8 +95,8 @@ typedef struct cwo_ctx cwo_ctx; /* opaque */
  * or a bad device ordinal, CWO_ERR_DEVICE if the device cannot be used. */
 cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes);
 
-/* Wait for all work the context launched, then free its scratch, tables and caches.
- * A null ctx is CWO_ERR_INVALID. */
+/* Finish every submitted job, wait for all work the context launched, stop its scheduler
+ * thread and free its scratch, tables and caches. A null ctx is CWO_ERR_INVALID. */
 cwo_status cwo_destroy(cwo_ctx* ctx);
 
 /* Angular spectrum propagation of one field (Sec. 2.1.4, Eq. ang3, padded per Sec. 2.1.6).
@@ -138,6 +138,34 @@ cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip
  * forward row FFT). Scratch: ny * 2nx complex64, plus iterations * ny doubles for E_k. */
 cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* hip_stream);
+
+/* ---- serving (continuous batching) ----------------------------------------------------
+ * cwo_submit queues one job and returns at once with a ticket; a scheduler thread of the
+ * context admits queued jobs in arrival order when one of its 4 slots (each with its own
+ * HIP stream, scratch and Fresnel-factor cache) is free and the job's footprint fits the
+ * context's HBM budget next to the jobs already running. A free slot takes the head job and
+ * the following ones that fit (up to 8) as one batch, run back to back on its stream (jobs
+ * on the same field form a z-stack), so requests that arrive while others run are admitted
+ * as slots and memory free up, and their work overlaps on the device.
+ * Footprint of a job: its input and output fields plus its padded scratch plane
+ * (16 nx ny + 8 ny 2nx bytes for complex64 storage). A job larger than the whole budget is
+ * rejected with CWO_ERR_NOMEM at submit; one that merely does not fit yet stays queued.
+ * The caller keeps in/out alive until the ticket reports done. Thread-safe. */
+
+/* Ticket states reported by cwo_poll: 0 queued, 1 running, 2 done, < 0 the job's error. */
+typedef struct {
+    int32_t state;
+    double t_submit, t_start, t_done; /* seconds since cwo_create, host steady clock */
+    size_t footprint;                 /* bytes reserved while the job ran */
+} cwo_ticket;
+
+cwo_status cwo_submit(cwo_ctx* ctx, const cwo_job* job, uint64_t* ticket);
+cwo_status cwo_poll(cwo_ctx* ctx, uint64_t ticket, int32_t* state);
+cwo_status cwo_ticket_info(cwo_ctx* ctx, uint64_t ticket, cwo_ticket* info);
+/* Forget a finished ticket (CWO_ERR_INVALID while it is queued or running). */
+cwo_status cwo_release(cwo_ctx* ctx, uint64_t ticket);
+/* Wait until every submitted job has finished; returns the context's sticky status. */
+cwo_status cwo_drain(cwo_ctx* ctx);
 
 /* Validate a parameter set for `kind` without touching any device: the same checks the
  * propagation calls run first. Returns CWO_OK, CWO_ERR_INVALID or CWO_ERR_UNSUPPORTED. */

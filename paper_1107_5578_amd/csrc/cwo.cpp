@@ -5,9 +5,13 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <list>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/cwo.h"
@@ -42,20 +46,65 @@ struct Buffer {
     size_t bytes = 0;
 };
 
-}  // namespace
-
-struct cwo_ctx {
-    int device = 0;
-    size_t budget = 0;
-    std::mutex mu;
-    cwo_status sticky = CWO_OK;
-    std::map<int, float2*> twiddles;  // FP32 exp(-2 pi i k / M) per M
+// Device memory one stream of work uses: the synchronous calls share the context's
+// workspace; each serving slot has its own (so slots never touch each other's scratch or
+// Fresnel factors, which are built on the slot's own stream).
+struct Workspace {
     Buffer scratch;                   // padded planes
     Buffer fwork;                     // FP64 chirps and twiddles for the Fresnel factors
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     Buffer gsnum;                     // per-row error partials of the ping-pong iteration
     Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
     std::list<FresnelEntry> fresnel;  // most recently used first
+    size_t budget = 0;                // 0: unbounded (serving slots are bounded by admission)
+    size_t held() const {
+        return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes;
+    }
+    void release() {
+        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork}) {
+            if (b->p) (void)hipFree(b->p);
+            b->p = nullptr;
+            b->bytes = 0;
+        }
+        for (auto& e : fresnel) (void)hipFree(e.h);
+        fresnel.clear();
+    }
+};
+
+struct Ticket {
+    cwo_job job;
+    int32_t state = 0;      // 0 queued, 1 running, 2 done, < 0 error status
+    size_t footprint = 0;   // bytes reserved from admission to completion
+    double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Workspace ws;
+    std::vector<uint64_t> running;  // tickets of the batch in flight
+};
+
+}  // namespace
+
+struct cwo_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::mutex mu;  // synchronous calls, twiddle tables, profiling
+    cwo_status sticky = CWO_OK;
+    std::map<int, float2*> twiddles;  // FP32 exp(-2 pi i k / M) per M
+    Workspace ws;                     // workspace of the synchronous calls
+    // serving
+    std::mutex qmu;  // tickets, queue, admission state
+    std::condition_variable qcv;
+    std::map<uint64_t, Ticket> tickets;
+    std::deque<uint64_t> queue;
+    uint64_t next_ticket = 1;
+    size_t reserved = 0;  // footprint of admitted, unfinished requests
+    std::vector<Slot> slots;
+    std::thread worker;
+    bool stop = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     // per-kernel timing
     bool profiling = false;
     struct Rec {
@@ -143,13 +192,9 @@ const float2* twiddle_table(cwo_ctx* c, int m, hipStream_t s, cwo_status* st) {
     return tw;
 }
 
-size_t held_bytes(const cwo_ctx* c) {
-    return c->scratch.bytes + c->fwork.bytes + c->ftab.bytes + c->gsnum.bytes + c->rwork.bytes;
-}
-
-void* ensure(cwo_ctx* c, Buffer& b, size_t bytes, cwo_status* st) {
+void* ensure(cwo_ctx* c, Workspace& ws, Buffer& b, size_t bytes, cwo_status* st) {
     if (b.bytes >= bytes) return b.p;
-    if (c->budget && held_bytes(c) - b.bytes + bytes > c->budget) {
+    if (ws.budget && ws.held() - b.bytes + bytes > ws.budget) {
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
@@ -257,21 +302,21 @@ cwo::FresnelPlanes fresnel_planes(const cwo_params* p, const Geometry& g, const 
 }
 
 // Fresnel factors of one plane, cached per parameter set.
-const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g, hipStream_t s,
-                              cwo_status* st) {
+const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, const Geometry& g,
+                              hipStream_t s, cwo_status* st) {
     FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z};
-    for (auto it = c->fresnel.begin(); it != c->fresnel.end(); ++it) {
+    for (auto it = ws.fresnel.begin(); it != ws.fresnel.end(); ++it) {
         if (it->key == key) {
-            c->fresnel.splice(c->fresnel.begin(), c->fresnel, it);
-            return c->fresnel.front().h;
+            ws.fresnel.splice(ws.fresnel.begin(), ws.fresnel, it);
+            return ws.fresnel.front().h;
         }
     }
     const size_t len = (size_t)(g.mx + g.my);
-    double2* work = (double2*)ensure(c, c->fwork, sizeof(double2) * len * 2, st);
+    double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len * 2, st);
     if (!work) return nullptr;
-    if (c->fresnel.size() >= kFresnelCacheEntries) {
-        FresnelEntry old = c->fresnel.back();
-        c->fresnel.pop_back();
+    if (ws.fresnel.size() >= kFresnelCacheEntries) {
+        FresnelEntry old = ws.fresnel.back();
+        ws.fresnel.pop_back();
         if (hipDeviceSynchronize() != hipSuccess) {
             *st = dev_fail(c);
             return nullptr;
@@ -292,7 +337,7 @@ const float2* fresnel_factors(cwo_ctx* c, const cwo_params* p, const Geometry& g
         *st = dev_fail(c);
         return nullptr;
     }
-    c->fresnel.push_front(e);
+    ws.fresnel.push_front(e);
     return e.h;
 }
 
@@ -302,21 +347,21 @@ cwo_status begin(cwo_ctx* c) {
     return CWO_OK;
 }
 
-cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
-                            hipStream_t s) {
+cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kind,
+                            const void* in, void* out, hipStream_t s) {
     cwo_status st = CWO_OK;
     const Geometry g = geometry(p);
     const float2* twx = twiddle_table(c, g.mx, s, &st);
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    void* buf = ensure(c, c->scratch, elem_bytes(p->precision) * (size_t)g.ny * g.mx, &st);
+    void* buf = ensure(c, ws, ws.scratch, elem_bytes(p->precision) * (size_t)g.ny * g.mx, &st);
     if (!buf) return st;
     const float2* fin = (const float2*)in;
     float2* fout = (float2*)out;
     const float2* h = nullptr;
     if (kind == CWO_FRESNEL_CONV) {
-        h = fresnel_factors(c, p, g, s, &st);
+        h = fresnel_factors(c, ws, p, g, s, &st);
         if (!h) return st;
     }
     cwo::Storage sto;  // complex64: no intermediate scaling, 1/(Mx My) at the end
@@ -331,7 +376,7 @@ cwo_status propagate_locked(cwo_ctx* c, const cwo_params* p, int kind, const voi
         sto.col_scale = 1.0f / (float)g.my;
         sto.out_scale = std::ldexp(1.0f, kx) / (float)g.mx;
         if (sto.prec == 1) {
-            float* rw = (float*)ensure(c, c->rwork, sizeof(float) * (2 + cwo::kRangeBlocks), &st);
+            float* rw = (float*)ensure(c, ws, ws.rwork, sizeof(float) * (2 + cwo::kRangeBlocks), &st);
             if (!rw) return st;
             CWO_HIP(c, cwo::launch_range_scale(fin, (size_t)g.ny * g.nx, rw, s));
             sto.dyn_scale = rw;
@@ -367,14 +412,14 @@ cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, 
     std::lock_guard<std::mutex> lock(c->mu);
     st = begin(c);
     if (st != CWO_OK) return st;
-    return propagate_locked(c, p, kind, in, out, (hipStream_t)stream);
+    return propagate_locked(c, c->ws, p, kind, in, out, (hipStream_t)stream);
 }
 
 // One field to nz distances; plane k goes to outs[k]. The row transform of the field
 // and the forward column transforms run once; planes are processed in chunks of at
 // most kZChunk that fit the scratch budget.
-cwo_status zstack_locked(cwo_ctx* c, const cwo_params* p, int kind, const double* z, int nz,
-                         const void* in, void* const* outs, hipStream_t s) {
+cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kind, const double* z,
+                         int nz, const void* in, void* const* outs, hipStream_t s) {
     cwo_status st = CWO_OK;
     const Geometry g = geometry(p);
     const float2* twx = twiddle_table(c, g.mx, s, &st);
@@ -385,24 +430,24 @@ cwo_status zstack_locked(cwo_ctx* c, const cwo_params* p, int kind, const double
     const size_t len = (size_t)(g.mx + g.my);
     // chunk size: the shared spectrum and all planes of a chunk within the budget
     int zc = std::min(nz, cwo::kZChunk);
-    if (c->budget) {
+    if (ws.budget) {
         const size_t fres = kind == CWO_FRESNEL_CONV ? (sizeof(float2) + sizeof(double2)) * len : 0;
         const size_t per_plane = sizeof(float2) * plane + fres;
         const size_t base = sizeof(float2) * plane + (kind == CWO_FRESNEL_CONV ? sizeof(double2) * len : 0);
-        if (c->budget < base + per_plane) return CWO_ERR_NOMEM;
-        const size_t fit = (c->budget - base) / per_plane;
+        if (ws.budget < base + per_plane) return CWO_ERR_NOMEM;
+        const size_t fit = (ws.budget - base) / per_plane;
         zc = (int)std::min<size_t>((size_t)zc, fit);
     }
-    float2* buf = (float2*)ensure(c, c->scratch, sizeof(float2) * plane * (size_t)(1 + zc), &st);
+    float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * plane * (size_t)(1 + zc), &st);
     if (!buf) return st;
     float2* spec = buf;
     float2* zbuf = buf + plane;
     float2* tabs = nullptr;
     double2* work = nullptr;
     if (kind == CWO_FRESNEL_CONV) {
-        tabs = (float2*)ensure(c, c->ftab, sizeof(float2) * len * zc, &st);
+        tabs = (float2*)ensure(c, ws, ws.ftab, sizeof(float2) * len * zc, &st);
         if (!tabs) return st;
-        work = (double2*)ensure(c, c->fwork, sizeof(double2) * len * (zc + 1), &st);
+        work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len * (zc + 1), &st);
         if (!work) return st;
     }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
@@ -445,9 +490,229 @@ bool same_group(const cwo_job& a, const cwo_job& b) {
            a.p.precision == b.p.precision && a.p.flags == b.p.flags;
 }
 
+cwo_status validate_jobs(const cwo_job* jobs, int njobs) {
+    for (int i = 0; i < njobs; ++i) {
+        const bool grouped = (i > 0 && same_group(jobs[i - 1], jobs[i])) ||
+                             (i + 1 < njobs && same_group(jobs[i], jobs[i + 1]));
+        cwo_status st = validate(&jobs[i].p, jobs[i].p.kind, !grouped);
+        if (st != CWO_OK) return st;
+        if (!jobs[i].in || !jobs[i].out) return CWO_ERR_INVALID;
+    }
+    return CWO_OK;
+}
+
+// Consecutive jobs on the same field and geometry run as one z-stack; the rest singly.
+cwo_status run_jobs(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int njobs, hipStream_t s) {
+    cwo_status st = CWO_OK;
+    int i = 0;
+    while (i < njobs) {
+        int j = i + 1;
+        while (j < njobs && same_group(jobs[i], jobs[j])) ++j;
+        if (j - i == 1) {
+            st = propagate_locked(c, ws, &jobs[i].p, jobs[i].p.kind, jobs[i].in, jobs[i].out, s);
+        } else {
+            std::vector<double> z;
+            std::vector<void*> outs;
+            for (int k = i; k < j; ++k) {
+                z.push_back(jobs[k].p.z);
+                outs.push_back(jobs[k].out);
+            }
+            st = zstack_locked(c, ws, &jobs[i].p, jobs[i].p.kind, z.data(), j - i, jobs[i].in,
+                               outs.data(), s);
+        }
+        if (st != CWO_OK) return st;
+        i = j;
+    }
+    return CWO_OK;
+}
+
+// ---- serving: continuous batching ------------------------------------------------
+//
+// A scheduler thread per context admits queued requests in arrival order when a slot
+// (its own HIP stream, workspace and completion event) is free and the request's
+// footprint fits the HBM budget next to the requests already running; a free slot takes
+// the head request and the following ones that fit (up to kMaxBatch) as one batch, run
+// back to back on its stream (requests on the same field form a z-stack). Slots run
+// concurrently, so work from different arrivals overlaps on the device.
+
+constexpr int kSlots = 4;
+constexpr int kMaxBatch = 8;
+
+double now_s(const cwo_ctx* c) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - c->t0).count();
+}
+
+// Bytes a request holds from admission to completion: its input and output fields and
+// its padded scratch plane.
+size_t footprint(const cwo_params* p) {
+    const Geometry g = geometry(p);
+    return 16 * (size_t)g.nx * g.ny + elem_bytes(p->precision) * (size_t)g.ny * g.mx;
+}
+
+void serve_loop(cwo_ctx* c) {
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(c->qmu);
+    while (true) {
+        // 1. retire finished batches
+        bool any_running = false;
+        for (Slot& sl : c->slots) {
+            if (sl.running.empty()) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) {
+                any_running = true;
+                continue;
+            }
+            const double t = now_s(c);
+            for (uint64_t id : sl.running) {
+                auto it = c->tickets.find(id);
+                if (it == c->tickets.end()) continue;
+                it->second.state = (q == hipSuccess) ? 2 : CWO_ERR_DEVICE;
+                it->second.t_done = t;
+                c->reserved -= it->second.footprint;
+            }
+            if (q != hipSuccess) c->sticky = CWO_ERR_DEVICE;
+            sl.running.clear();
+        }
+        // 2. admit and launch
+        for (Slot& sl : c->slots) {
+            if (!sl.running.empty() || c->queue.empty()) continue;
+            std::vector<cwo_job> batch;
+            std::vector<uint64_t> ids;
+            while (!c->queue.empty() && (int)batch.size() < kMaxBatch) {
+                Ticket& tk = c->tickets[c->queue.front()];
+                if (c->budget && c->reserved + tk.footprint > c->budget) break;  // FIFO: wait
+                c->reserved += tk.footprint;
+                tk.state = 1;
+                tk.t_start = now_s(c);
+                batch.push_back(tk.job);
+                ids.push_back(c->queue.front());
+                c->queue.pop_front();
+            }
+            if (batch.empty()) break;  // the head does not fit yet
+            cwo_status st;
+            {
+                std::lock_guard<std::mutex> g(c->mu);  // twiddle tables, profiling state
+                st = c->sticky != CWO_OK ? c->sticky
+                                         : run_jobs(c, sl.ws, batch.data(), (int)batch.size(), sl.stream);
+                if (st == CWO_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = dev_fail(c);
+            }
+            if (st != CWO_OK) {
+                for (uint64_t id : ids) {
+                    Ticket& tk = c->tickets[id];
+                    tk.state = st;
+                    tk.t_done = now_s(c);
+                    c->reserved -= tk.footprint;
+                }
+                continue;
+            }
+            sl.running = ids;
+            any_running = true;
+        }
+        c->qcv.notify_all();  // progress for drain()
+        if (c->stop && c->queue.empty() && !any_running) break;
+        if (any_running)
+            c->qcv.wait_for(lk, std::chrono::microseconds(20));
+        else
+            c->qcv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
+    }
+}
+
+cwo_status start_serving(cwo_ctx* c) {
+    if (c->worker.joinable()) return CWO_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return dev_fail(c);
+    c->slots.resize(kSlots);
+    for (Slot& sl : c->slots) {
+        // default priority streams
+        if (!sl.stream && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+            return dev_fail(c);
+        if (!sl.done && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+            return dev_fail(c);
+    }
+    c->stop = false;
+    c->worker = std::thread(serve_loop, c);
+    return CWO_OK;
+}
+
+void stop_serving(cwo_ctx* c) {
+    {
+        std::lock_guard<std::mutex> lk(c->qmu);
+        c->stop = true;
+    }
+    c->qcv.notify_all();
+    if (c->worker.joinable()) c->worker.join();
+}
+
 }  // namespace
 
 extern "C" {
+
+cwo_status cwo_submit(cwo_ctx* c, const cwo_job* job, uint64_t* ticket) {
+    if (!c || !job || !ticket) return CWO_ERR_INVALID;
+    const int kind = job->p.kind;
+    cwo_status st = validate(&job->p, kind, true);
+    if (st != CWO_OK) return st;
+    if (!job->in || !job->out) return CWO_ERR_INVALID;
+    const size_t fp = footprint(&job->p);
+    if (c->budget && fp > c->budget) return CWO_ERR_NOMEM;
+    std::lock_guard<std::mutex> lk(c->qmu);
+    if (c->sticky != CWO_OK) return c->sticky;
+    if (!c->worker.joinable() && (st = start_serving(c)) != CWO_OK) return st;
+    const uint64_t id = c->next_ticket++;
+    Ticket tk;
+    tk.job = *job;
+    tk.footprint = fp;
+    tk.t_submit = now_s(c);
+    c->tickets.emplace(id, tk);
+    c->queue.push_back(id);
+    *ticket = id;
+    c->qcv.notify_all();
+    return CWO_OK;
+}
+
+cwo_status cwo_poll(cwo_ctx* c, uint64_t ticket, int32_t* state) {
+    if (!c || !state) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(c->qmu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return CWO_ERR_NOTFOUND;
+    *state = it->second.state;
+    return CWO_OK;
+}
+
+cwo_status cwo_ticket_info(cwo_ctx* c, uint64_t ticket, cwo_ticket* info) {
+    if (!c || !info) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(c->qmu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return CWO_ERR_NOTFOUND;
+    info->state = it->second.state;
+    info->t_submit = it->second.t_submit;
+    info->t_start = it->second.t_start;
+    info->t_done = it->second.t_done;
+    info->footprint = it->second.footprint;
+    return CWO_OK;
+}
+
+cwo_status cwo_release(cwo_ctx* c, uint64_t ticket) {
+    if (!c) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(c->qmu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return CWO_ERR_NOTFOUND;
+    if (it->second.state == 0 || it->second.state == 1) return CWO_ERR_INVALID;  // not finished
+    c->tickets.erase(it);
+    return CWO_OK;
+}
+
+cwo_status cwo_drain(cwo_ctx* c) {
+    if (!c) return CWO_ERR_INVALID;
+    std::unique_lock<std::mutex> lk(c->qmu);
+    c->qcv.wait(lk, [&] {
+        if (!c->queue.empty()) return false;
+        for (const Slot& sl : c->slots)
+            if (!sl.running.empty()) return false;
+        return true;
+    });
+    return c->sticky;
+}
+
 
 cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes) {
     if (!ctx) return CWO_ERR_INVALID;
@@ -459,21 +724,26 @@ cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes) {
     cwo_ctx* c = new cwo_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
+    c->ws.budget = hbm_budget_bytes;
     *ctx = c;
     return CWO_OK;
 }
 
 cwo_status cwo_destroy(cwo_ctx* c) {
     if (!c) return CWO_ERR_INVALID;
+    stop_serving(c);  // finishes every submitted request first
     {
         std::lock_guard<std::mutex> lock(c->mu);
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
         (void)drain_profile(c);
         for (auto& kv : c->twiddles) (void)hipFree(kv.second);
-        for (auto& e : c->fresnel) (void)hipFree(e.h);
-        for (Buffer* b : {&c->scratch, &c->fwork, &c->ftab, &c->gsnum, &c->rwork})
-            if (b->p) (void)hipFree(b->p);
+        c->ws.release();
+        for (Slot& sl : c->slots) {
+            sl.ws.release();
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
         for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
     }
     delete c;
@@ -501,42 +771,16 @@ cwo_status cwo_zstack(cwo_ctx* c, const cwo_params* p, const double* z, int32_t 
     for (int k = 0; k < nz; ++k) outs[k] = (float2*)out + (size_t)k * g.ny * g.nx;
     std::lock_guard<std::mutex> lock(c->mu);
     if ((st = begin(c)) != CWO_OK) return st;
-    return zstack_locked(c, p, kind, z, nz, in, outs.data(), (hipStream_t)stream);
+    return zstack_locked(c, c->ws, p, kind, z, nz, in, outs.data(), (hipStream_t)stream);
 }
 
 cwo_status cwo_batch(cwo_ctx* c, const cwo_job* jobs, int32_t njobs, void* stream) {
     if (!c || (!jobs && njobs > 0) || njobs < 0) return CWO_ERR_INVALID;
-    cwo_status st;
-    for (int i = 0; i < njobs; ++i) {
-        const bool grouped = (i > 0 && same_group(jobs[i - 1], jobs[i])) ||
-                             (i + 1 < njobs && same_group(jobs[i], jobs[i + 1]));
-        if ((st = validate(&jobs[i].p, jobs[i].p.kind, !grouped)) != CWO_OK) return st;
-        if (!jobs[i].in || !jobs[i].out) return CWO_ERR_INVALID;
-    }
+    cwo_status st = validate_jobs(jobs, njobs);
+    if (st != CWO_OK) return st;
     std::lock_guard<std::mutex> lock(c->mu);
     if ((st = begin(c)) != CWO_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    // consecutive jobs on the same field and geometry form one z-stack
-    int i = 0;
-    while (i < njobs) {
-        int j = i + 1;
-        while (j < njobs && same_group(jobs[i], jobs[j])) ++j;
-        if (j - i == 1) {
-            st = propagate_locked(c, &jobs[i].p, jobs[i].p.kind, jobs[i].in, jobs[i].out, s);
-        } else {
-            std::vector<double> z;
-            std::vector<void*> outs;
-            for (int k = i; k < j; ++k) {
-                z.push_back(jobs[k].p.z);
-                outs.push_back(jobs[k].out);
-            }
-            st = zstack_locked(c, &jobs[i].p, jobs[i].p.kind, z.data(), j - i, jobs[i].in,
-                               outs.data(), s);
-        }
-        if (st != CWO_OK) return st;
-        i = j;
-    }
-    return CWO_OK;
+    return run_jobs(c, c->ws, jobs, njobs, (hipStream_t)stream);
 }
 
 cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float* a2, void* u,
@@ -553,11 +797,12 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    float2* spec = (float2*)ensure(c, c->scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    float2* spec = (float2*)ensure(c, c->ws, c->ws.scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
     if (!spec) return st;
     double* num = nullptr;
     if (errors) {
-        num = (double*)ensure(c, c->gsnum, sizeof(double) * ((size_t)iterations * g.ny + 1), &st);
+        num = (double*)ensure(c, c->ws, c->ws.gsnum, sizeof(double) * ((size_t)iterations * g.ny + 1),
+                              &st);
         if (!num) return st;
     }
     const cwo::AsmScalars fwd = asm_scalars(p, g, p->z), back = asm_scalars(p, g, -p->z);

@@ -68,6 +68,15 @@ class Job(ctypes.Structure):
     _fields_ = [("p", Params), ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("footprint", ctypes.c_size_t)]
+
+
+QUEUED, RUNNING, DONE = 0, 1, 2
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -87,6 +96,13 @@ SIGNATURES = {
     "cwo_gs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                 ctypes.c_void_p]),
+    "cwo_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job),
+                                    ctypes.POINTER(ctypes.c_uint64)]),
+    "cwo_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "cwo_ticket_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.POINTER(TicketInfo)]),
+    "cwo_release": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
+    "cwo_drain": (ctypes.c_int32, [ctypes.c_void_p]),
     "cwo_check_params": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.c_int32]),
     "cwo_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "cwo_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -265,6 +281,49 @@ class Context:
         if st != CWO_OK:
             raise CwoError(st, "cwo_gs")
         return err[:int(iterations)] if err is not None else None
+
+    # -- serving --------------------------------------------------------------
+    def submit(self, kind, u, out, dx=10e-6, dy=None, wavelength=633e-9, z=0.1,
+               precision="f32"):
+        """Queue one propagation; returns a ticket. u and out must stay alive until done."""
+        u = self._field(u)
+        out = self._field(out)
+        ny, nx = u.shape
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        job = Job()
+        job.p = make_params(nx, ny, dx, dy, wavelength, z, k, precision)
+        job.inp = u.data_ptr()
+        job.out = out.data_ptr()
+        t = ctypes.c_uint64()
+        st = self._lib.cwo_submit(self.handle, ctypes.byref(job), ctypes.byref(t))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_submit")
+        return t.value
+
+    def poll(self, ticket):
+        state = ctypes.c_int32()
+        st = self._lib.cwo_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(state))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_poll")
+        return state.value
+
+    def info(self, ticket):
+        i = TicketInfo()
+        st = self._lib.cwo_ticket_info(self.handle, ctypes.c_uint64(ticket), ctypes.byref(i))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_ticket_info")
+        return {"state": i.state, "t_submit": i.t_submit, "t_start": i.t_start,
+                "t_done": i.t_done, "footprint": i.footprint}
+
+    def release(self, ticket):
+        st = self._lib.cwo_release(self.handle, ctypes.c_uint64(ticket))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_release")
+
+    def drain(self):
+        st = self._lib.cwo_drain(self.handle)
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_drain")
 
     def batch(self, jobs, stream=None):
         """Run a list of (kind, u, out, dict(dx=, dy=, wavelength=, z=, ...)) jobs in order."""

@@ -1,0 +1,132 @@
+"""GPU tests of the serving loop (cwo_submit / cwo_poll, continuous batching).
+
+The key property: each result is the same alone and in the mix. Every request of a
+mixed stream (sizes, kinds, distances, wavelengths, same-field groups) is also run on
+its own through the synchronous call, and the two outputs must agree to relative L2
+<= 1e-6 (the serving slots run the same kernels; only z-stack grouping may change the
+rounding order). Admission by memory and the error paths are checked too.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return t
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_alone_vs_mix(torch):
+    from paper_1107_5578_amd import cwo
+    rng = np.random.default_rng(55)
+    server = cwo.Context(0, hbm_budget_bytes=256 << 20)
+    alone = cwo.Context(0)
+    try:
+        fields = {n: torch.from_numpy(W.uniform_random_field(n, 7000 + n)).cuda()
+                  for n in (64, 128, 256, 512, 1024)}
+        reqs = []
+        for i in range(40):
+            n = int(rng.choice([64, 128, 256, 512, 1024]))
+            kind = "asm" if rng.random() < 0.5 else "fresnel"
+            kw = dict(dx=8e-6, wavelength=float(rng.choice([473e-9, 532e-9, 633e-9])),
+                      z=float(rng.uniform(0.01, 1.0)))
+            reqs.append((kind, fields[n], kw))
+        # two requests on the same field back to back form a z-stack inside one batch
+        reqs.insert(5, ("asm", fields[256], dict(dx=8e-6, wavelength=532e-9, z=0.2)))
+        reqs.insert(6, ("asm", fields[256], dict(dx=8e-6, wavelength=532e-9, z=0.3)))
+        outs = [torch.empty_like(u) for _, u, _ in reqs]
+        note("serving %d mixed requests" % len(reqs))
+        tickets = [server.submit(kind, u, o, **kw) for (kind, u, kw), o in zip(reqs, outs)]
+        server.drain()
+        worst = 0.0
+        for t, (kind, u, kw), o in zip(tickets, reqs, outs):
+            assert server.poll(t) == cwo.DONE
+            inf = server.info(t)
+            assert inf["t_submit"] <= inf["t_start"] <= inf["t_done"]
+            ref = (alone.asm if kind == "asm" else alone.fresnel)(u, kw["dx"], kw["dx"],
+                                                                   kw["wavelength"], kw["z"])
+            torch.cuda.synchronize()
+            worst = max(worst, D.rel_l2(o.cpu().numpy(), ref.cpu().numpy().astype(np.complex128)))
+            server.release(t)
+        note("alone vs mix: worst rel_l2 = %.3e" % worst)
+        assert worst <= 1e-6
+        # and one request of the mix against the FP64 oracle
+        kind, u, kw = reqs[-1]
+        ref = D.propagate(u.cpu().numpy(), D.ASM if kind == "asm" else D.FRESNEL, kw["dx"], kw["dx"],
+                          kw["wavelength"], kw["z"])
+        assert D.rel_l2(outs[-1].cpu().numpy(), ref) <= 1e-5
+    finally:
+        server.close()
+        alone.close()
+
+
+def test_admission_by_memory(torch):
+    from paper_1107_5578_amd import cwo
+    n = 512
+    fp = 16 * n * n + 8 * n * 2 * n
+    server = cwo.Context(0, hbm_budget_bytes=2 * fp)   # at most two requests resident at once
+    try:
+        u = torch.from_numpy(W.uniform_random_field(n, 3)).cuda()
+        outs = [torch.empty_like(u) for _ in range(12)]
+        tickets = [server.submit("asm", u, o, dx=8e-6, wavelength=532e-9, z=0.1 + 0.01 * i)
+                   for i, o in enumerate(outs)]
+        seen_running = 0
+        deadline = time.time() + 60
+        while time.time() < deadline:
+            states = [server.poll(t) for t in tickets]
+            seen_running = max(seen_running, sum(1 for s in states if s == cwo.RUNNING))
+            if all(s == cwo.DONE for s in states):
+                break
+            time.sleep(0.0005)
+        server.drain()
+        assert all(server.poll(t) == cwo.DONE for t in tickets)
+        assert seen_running <= 2
+        infos = [server.info(t) for t in tickets]
+        assert all(i["footprint"] == fp for i in infos)
+        # FIFO admission: starts are in submission order
+        starts = [i["t_start"] for i in infos]
+        assert starts == sorted(starts)
+        big = torch.zeros((1024, 1024), dtype=torch.complex64, device="cuda")
+        with pytest.raises(cwo.CwoError) as e:
+            server.submit("asm", big, torch.empty_like(big), z=0.1)
+        assert e.value.status == cwo.CWO_ERR_NOMEM
+        ref = D.asm(u.cpu().numpy(), 8e-6, 8e-6, 532e-9, 0.1 + 0.01 * 11)
+        assert D.rel_l2(outs[11].cpu().numpy(), ref) <= 1e-5
+    finally:
+        server.close()
+
+
+def test_ticket_errors(torch):
+    from paper_1107_5578_amd import cwo
+    server = cwo.Context(0)
+    try:
+        with pytest.raises(cwo.CwoError) as e:
+            server.poll(12345)
+        assert e.value.status == cwo.CWO_ERR_NOTFOUND
+        u = torch.zeros((64, 64), dtype=torch.complex64, device="cuda")
+        with pytest.raises(cwo.CwoError) as e:
+            server.submit("fresnel", u, torch.empty_like(u), z=0.0)
+        assert e.value.status == cwo.CWO_ERR_INVALID
+        t = server.submit("asm", u, torch.empty_like(u), z=0.1)
+        server.drain()
+        server.release(t)
+        with pytest.raises(cwo.CwoError) as e:
+            server.release(t)
+        assert e.value.status == cwo.CWO_ERR_NOTFOUND
+    finally:
+        server.close()
