@@ -199,6 +199,38 @@ struct Plan {
     static constexpr int ns(int p) { return p == 0 ? 1 : (1 << FIRST_BITS) << (LR * (p - 1)); }
 };
 
+// Twiddles of every pass for one thread, loaded once (they depend on the thread index
+// only): W_{Ns*RP}^{(b mod Ns)*kk} for each butterfly b = j + i*T and kk = 1..RP-1,
+// stored at w[pass][i*RP + kk]. Loading them up front takes the twiddle loads off the
+// critical path between LDS exchanges, and a forward and an inverse transform of the
+// same length share them (the inverse conjugates on use).
+template <int M, int E>
+struct TwCache {
+    using PL = Plan<M, E>;
+    float2 w[PL::PASSES][E];
+    __device__ __forceinline__ void load(int j, const float2* __restrict__ tw) {
+        constexpr int T = PL::T;
+        [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+            (([&] {
+                 constexpr int p = Ps;
+                 constexpr int RP = PL::radix(p);
+                 constexpr int NS = PL::ns(p);
+                 constexpr int NB = E / RP;
+                 if constexpr (NS > 1) {
+                     constexpr int STEP = M / (NS * RP);
+#pragma unroll
+                     for (int i = 0; i < NB; ++i) {
+                         const int k = (j + i * T) & (NS - 1);
+#pragma unroll
+                         for (int kk = 1; kk < RP; ++kk) w[p][i * RP + kk] = tw[k * kk * STEP];
+                     }
+                 }
+             }()),
+             ...);
+        }(std::make_integer_sequence<int, PL::PASSES>{});
+    }
+};
+
 // LDS slot of element e: one pad slot every 16 elements keeps the strided
 // Stockham writes spread over the banks
 __device__ __forceinline__ int lds_slot(int e) { return e + (e >> 4); }
@@ -237,10 +269,13 @@ __device__ __forceinline__ void lds_get(const float2* lds, int slot, float2 (&x)
 }
 
 // One Stockham pass over P transforms that share twiddles. Writes results to LDS
-// (intermediate pass) or back into registers in natural order (last pass).
-template <int M, int E, int P, int RP, int NS, bool LAST, int DIR>
+// (intermediate pass) or back into registers in natural order (last pass). With SPLIT
+// (P == 2 only) the LDS holds one transform at a time: transform 0 is written here and
+// transform 1's outputs are kept in `held` for the second half of the exchange.
+template <int M, int E, int P, int RP, int NS, bool LAST, int DIR, bool SPLIT, bool PRE>
 __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, int j,
-                                              const float2* __restrict__ tw) {
+                                              const float2* __restrict__ tw,
+                                              const float2 (&wpre)[E], float2 (&held)[E]) {
     constexpr int T = M / E;
     constexpr int NB = E / RP;  // butterflies per thread and transform
     float2 out[P][E];
@@ -252,7 +287,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
         if constexpr (NS > 1) {
             constexpr int STEP = M / (NS * RP);
 #pragma unroll
-            for (int kk = 1; kk < RP; ++kk) w[kk] = tw[k * kk * STEP];
+            for (int kk = 1; kk < RP; ++kk) w[kk] = PRE ? wpre[i * RP + kk] : tw[k * kk * STEP];
         }
         float2 u[P][RP];
 #pragma unroll
@@ -270,6 +305,13 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
             for (int p = 0; p < P; ++p)
 #pragma unroll
                 for (int kk = 0; kk < RP; ++kk) out[p][i + kk * NB] = u[p][kk];
+        } else if constexpr (SPLIT) {
+            const int base = (b / NS) * NS * RP + k;
+#pragma unroll
+            for (int kk = 0; kk < RP; ++kk) {
+                lds[lds_slot(base + kk * NS)] = u[0][kk];
+                held[i * RP + kk] = u[1][kk];
+            }
         } else {
             const int base = (b / NS) * NS * RP + k;
 #pragma unroll
@@ -291,9 +333,13 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
 
 // Full transform of P sequences at once. On entry v[p][r] = x_p[j + r*T]; on exit
 // v[p][r] = X_p[j + r*T]. All threads of the block must call it (block barriers).
-template <int M, int E, int P, int DIR>
-__device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
-                                    const float2* __restrict__ tw) {
+// SPLIT halves the LDS footprint (one float2 slot per element) at the cost of two more
+// barriers per exchange.
+template <int M, int E, int P, int DIR, bool SPLIT = false, bool PRE = false>
+__device__ __forceinline__ void fft_impl(float2 (&v)[P][E], float2* lds, int j,
+                                         const float2* __restrict__ tw,
+                                         const TwCache<M, E>* twc) {
+    static_assert(!SPLIT || P == 2, "split exchange is for two transforms");
     using PL = Plan<M, E>;
     constexpr int T = PL::T;
     [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
@@ -302,21 +348,59 @@ __device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
              constexpr int RP = PL::radix(p);
              constexpr int NS = PL::ns(p);
              constexpr bool LAST = (p == PL::PASSES - 1);
-             stockham_pass<M, E, P, RP, NS, LAST, DIR>(v, lds, j, tw);
+             float2 held[E];
+             if constexpr (PRE)
+                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, true>(v, lds, j, tw, twc->w[p], held);
+             else
+                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, false>(v, lds, j, tw, held, held);
              if constexpr (!LAST) {
-                 lds_barrier();
+                 if constexpr (SPLIT) {
+                     lds_barrier();
 #pragma unroll
-                 for (int r = 0; r < E; ++r) {
-                     float2 x[P];
-                     lds_get<P>(lds, lds_slot(j + r * T), x);
+                     for (int r = 0; r < E; ++r) v[0][r] = lds[lds_slot(j + r * T)];
+                     lds_barrier();
+                     constexpr int NB = E / RP;
 #pragma unroll
-                     for (int q = 0; q < P; ++q) v[q][r] = x[q];
+                     for (int i = 0; i < NB; ++i) {
+                         const int b = j + i * T;
+                         const int k = b & (NS - 1);
+                         const int base = (b / NS) * NS * RP + k;
+#pragma unroll
+                         for (int kk = 0; kk < RP; ++kk) lds[lds_slot(base + kk * NS)] = held[i * RP + kk];
+                     }
+                     lds_barrier();
+#pragma unroll
+                     for (int r = 0; r < E; ++r) v[P - 1][r] = lds[lds_slot(j + r * T)];
+                     lds_barrier();
+                 } else {
+                     lds_barrier();
+#pragma unroll
+                     for (int r = 0; r < E; ++r) {
+                         float2 x[P];
+                         lds_get<P>(lds, lds_slot(j + r * T), x);
+#pragma unroll
+                         for (int q = 0; q < P; ++q) v[q][r] = x[q];
+                     }
+                     lds_barrier();
                  }
-                 lds_barrier();
              }
          }()),
          ...);
     }(std::make_integer_sequence<int, PL::PASSES>{});
+}
+
+// Transform with twiddles loaded from the table in each pass.
+template <int M, int E, int P, int DIR, bool SPLIT = false>
+__device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
+                                    const float2* __restrict__ tw) {
+    fft_impl<M, E, P, DIR, SPLIT, false>(v, lds, j, tw, nullptr);
+}
+
+// Transform with the thread's twiddles preloaded in registers.
+template <int M, int E, int P, int DIR, bool SPLIT = false>
+__device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
+                                    const TwCache<M, E>& twc) {
+    fft_impl<M, E, P, DIR, SPLIT, true>(v, lds, j, nullptr, &twc);
 }
 
 }  // namespace cwo

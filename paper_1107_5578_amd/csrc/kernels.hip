@@ -23,6 +23,7 @@
 //             h_F factorises into two 1-D transforms of chirps, computed here
 //             in FP64 by direct summation.
 #include <cmath>
+#include <cstdlib>
 #include <cstddef>
 #include <cstdint>
 #include <type_traits>
@@ -51,9 +52,10 @@ struct ColCfg {
     static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
     static constexpr int T = M / E;
     // two columns per thread, except at M = 8192 where 32 values per column already
-    // fill the register budget
+    // fill the register budget; the two columns share one LDS buffer (split exchange)
     static constexpr int P = (M == 8192) ? 1 : 2;
-    static constexpr int LDS_PAIR = P * lds_elems<M>();  // float2 entries per pair
+    static constexpr bool SPLIT = false;
+    static constexpr int LDS_PAIR = (SPLIT ? 1 : P) * lds_elems<M>();  // float2 entries per pair
     static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
     static constexpr int BY_LDS0 = (72 * 1024) / (LDS_PAIR * 8);
     static constexpr int BY_LDS = BY_LDS0 < 1 ? 1 : BY_LDS0;
@@ -61,6 +63,7 @@ struct ColCfg {
     static constexpr int PAIRS = PAIRS0 > 16 ? 16 : PAIRS0;
     static constexpr int THREADS = T * PAIRS;
     static constexpr int COLS = P * PAIRS;  // columns per block
+    static constexpr int WAVES_PER_EU = 2;
 };
 
 // z-stack column pass: the forward spectrum stays in registers while each plane's
@@ -113,6 +116,8 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
     const float2* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * nx;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -128,7 +133,8 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
 #pragma unroll
         for (int r = 0; r < E; ++r) v[0][r] = make_float2(v[0][r].x * f, v[0][r].y * f);
     }
-    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
+    if constexpr (E == 16) fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+    else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
         typename ST::E* dst = out + blockIdx.y * out_plane + (size_t)row * M;
 #pragma unroll
@@ -238,7 +244,7 @@ struct FresnelH {
 };
 
 template <int M, bool HALF, class HF, class ST>
-__global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(typename ST::E* __restrict__ buf,
+__global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_col(typename ST::E* __restrict__ buf,
                                                               int ny, int mx, size_t plane, HF hf,
                                                               float hscale,
                                                               const float2* __restrict__ tw) {
@@ -255,6 +261,8 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(typename ST::E* __re
     const bool active = col0 < mx;                 // blocks may overhang narrow planes
     const int col = active ? col0 : 0;
     SE* base = buf + blockIdx.y * plane + col;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
     float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -273,7 +281,8 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(typename ST::E* __re
     typename HF::Col hc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
-    fft<M, E, P, FWD>(v, my_lds, j, tw);
+    if constexpr (E == 16) fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
+    else fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, tw);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const typename HF::Row hr = hf.row(j + r * T);
@@ -284,7 +293,8 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col(typename ST::E* __re
             v[p][r] = cmul(v[p][r], h);
         }
     }
-    fft<M, E, P, INV>(v, my_lds, j, tw);
+    if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
+    else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
@@ -483,10 +493,13 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
     const typename ST::E* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * M;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[0][r] = valid ? ST::dec(src[j + r * T]) : make_float2(0.f, 0.f);
-    fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
+    if constexpr (E == 16) fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
+    else fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
     if (valid) {
         float2* dst = outs(blockIdx.y) + (size_t)row * nx;
 #pragma unroll
