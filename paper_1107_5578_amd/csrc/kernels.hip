@@ -142,6 +142,59 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
     }
 }
 
+// Persistent form: a grid of resident blocks walks the rows (block b takes row groups
+// b, b + G, ...) and issues the next group's loads before transforming the current one.
+template <int M, bool HALF, class ST>
+__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(const float2* __restrict__ in,
+                                                                     typename ST::E* __restrict__ out,
+                                                                     int nx, int ny, int batch,
+                                                                     size_t in_plane, size_t out_plane,
+                                                                     RowScale sc,
+                                                                     const float2* __restrict__ tw) {
+    using C = RowCfg<M>;
+    constexpr int E = C::E, T = C::T;
+    constexpr int NL = HALF ? E / 2 : E;
+    __shared__ float2 lds[C::RPB * lds_elems<M>()];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    const float f = sc.dyn ? sc.in * *sc.dyn : sc.in;
+    const int rows = ny * batch;
+    const int groups = (rows + C::RPB - 1) / C::RPB;
+    TwCache<M, E> twc;
+    twc.load(j, tw);
+    auto load = [&](int g, float2 (&d)[NL]) {
+        const int w = g * C::RPB + sub;
+        const bool ok = w < rows;
+        const int pl = ok ? w / ny : 0, row = ok ? w - pl * ny : 0;
+        const float2* src = in + pl * in_plane + (size_t)row * nx;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int x = j + r * T;
+            d[r] = (ok && (HALF || x < nx)) ? src[x] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 cur[NL], nxt[NL];
+    int g = blockIdx.x;
+    if (g < groups) load(g, cur);
+    for (; g < groups; g += gridDim.x) {
+        if (g + (int)gridDim.x < groups) load(g + gridDim.x, nxt);
+        float2 v[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+            v[0][r] = r < NL ? make_float2(cur[r].x * f, cur[r].y * f) : make_float2(0.f, 0.f);
+        fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+        const int w = g * C::RPB + sub;
+        if (w < rows) {
+            const int pl = w / ny, row = w - pl * ny;
+            typename ST::E* dst = out + pl * out_plane + (size_t)row * M;
+#pragma unroll
+            for (int r = 0; r < E; ++r) dst[j + r * T] = ST::enc(v[0][r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NL; ++r) cur[r] = nxt[r];
+    }
+}
+
 // ---- column pass: FFT, transfer function, IFFT, crop --------------------------
 
 // Exact form, for any parameters: per bin in FP64, the propagating test s <= 1
@@ -515,6 +568,55 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
     }
 }
 
+// Persistent form of the row inverse (see k_row_fwd_pf).
+template <int M, bool HALF, class OUT, class ST>
+__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv_pf(
+    const typename ST::E* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
+    float scale, const float* __restrict__ dyn_inv, const float2* __restrict__ tw) {
+    using C = RowCfg<M>;
+    constexpr int E = C::E, T = C::T;
+    __shared__ float2 lds[C::RPB * lds_elems<M>()];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    if (dyn_inv) scale *= *dyn_inv;
+    const int rows = ny * batch;
+    const int groups = (rows + C::RPB - 1) / C::RPB;
+    TwCache<M, E> twc;
+    twc.load(j, tw);
+    using SE = typename ST::E;
+    auto load = [&](int g, SE (&d)[E]) {
+        const int w = g * C::RPB + sub;
+        const bool ok = w < rows;
+        const int pl = ok ? w / ny : 0, row = ok ? w - pl * ny : 0;
+        const SE* src = in + pl * in_plane + (size_t)row * M;
+#pragma unroll
+        for (int r = 0; r < E; ++r) d[r] = src[j + r * T];
+    };
+    SE cur[E], nxt[E];
+    int g = blockIdx.x;
+    if (g < groups) load(g, cur);
+    for (; g < groups; g += gridDim.x) {
+        if (g + (int)gridDim.x < groups) load(g + gridDim.x, nxt);
+        float2 v[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[0][r] = ST::dec(cur[r]);
+        fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
+        const int w = g * C::RPB + sub;
+        if (w < rows) {
+            const int pl = w / ny, row = w - pl * ny;
+            float2* dst = outs(pl) + (size_t)row * nx;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int x = j + r * T;
+                if (HALF ? (r < E / 2) : (x < nx))
+                    dst[x] = make_float2(v[0][r].x * scale, v[0][r].y * scale);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) cur[r] = nxt[r];
+    }
+}
+
 // ---- ping-pong iteration row kernel ----------------------------------------------
 //
 // Row inverse transform, crop, amplitude constraint and re-padded forward transform
@@ -737,12 +839,39 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class K>
+static int resident_blocks(K kernel, int threads, int items) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess ||
+        occ <= 0)
+        occ = 1;
+    const long long n = (long long)occ * cus;
+    return (int)(items < n ? items : n);
+}
+
 template <class ST>
 static hipError_t launch_row_fwd_t(const float2* in, void* out, int nx, int ny, int mx, int batch,
                                    size_t in_plane, size_t out_plane, RowScale sc,
                                    const float2* tw, hipStream_t s) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
+    // persistent form with prefetch where rows are long enough to fill whole blocks
+    if (half && mx >= 1024 && mx != 8192) {
+        CWO_DISPATCH_M(mx, {
+            if constexpr (RowCfg<MM>::E == 16) {
+                using C = RowCfg<MM>;
+                const int groups = (ny * batch + C::RPB - 1) / C::RPB;
+                auto k = k_row_fwd_pf<MM, true, ST>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, in, (SE*)out, nx, ny, batch, in_plane, out_plane, sc, tw);
+            }
+        });
+        return hipGetLastError();
+    }
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
@@ -846,6 +975,19 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
                                    const float2* tw, hipStream_t s) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
+    if (half && mx >= 1024 && mx != 8192) {
+        CWO_DISPATCH_M(mx, {
+            if constexpr (RowCfg<MM>::E == 16) {
+                using C = RowCfg<MM>;
+                const int groups = (ny * batch + C::RPB - 1) / C::RPB;
+                auto k = k_row_inv_pf<MM, true, OUT, ST>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
+                                   dyn_inv, tw);
+            }
+        });
+        return hipGetLastError();
+    }
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
