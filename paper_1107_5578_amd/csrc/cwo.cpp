@@ -51,7 +51,7 @@ struct Buffer {
 // Fresnel factors, which are built on the slot's own stream).
 struct Workspace {
     Buffer scratch;                   // padded planes
-    Buffer fwork;                     // FP64 chirps and twiddles for the Fresnel factors
+    Buffer fwork;                     // FP64 twiddles for the Fresnel factors
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     Buffer gsnum;                     // per-row error partials of the ping-pong iteration
     Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
@@ -312,7 +312,7 @@ const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, co
         }
     }
     const size_t len = (size_t)(g.mx + g.my);
-    double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len * 2, st);
+    double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len, st);
     if (!work) return nullptr;
     if (ws.fresnel.size() >= kFresnelCacheEntries) {
         FresnelEntry old = ws.fresnel.back();
@@ -431,7 +431,7 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
     // chunk size: the shared spectrum and all planes of a chunk within the budget
     int zc = std::min(nz, cwo::kZChunk);
     if (ws.budget) {
-        const size_t fres = kind == CWO_FRESNEL_CONV ? (sizeof(float2) + sizeof(double2)) * len : 0;
+        const size_t fres = kind == CWO_FRESNEL_CONV ? sizeof(float2) * len : 0;
         const size_t per_plane = sizeof(float2) * plane + fres;
         const size_t base = sizeof(float2) * plane + (kind == CWO_FRESNEL_CONV ? sizeof(double2) * len : 0);
         if (ws.budget < base + per_plane) return CWO_ERR_NOMEM;
@@ -447,7 +447,7 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
     if (kind == CWO_FRESNEL_CONV) {
         tabs = (float2*)ensure(c, ws, ws.ftab, sizeof(float2) * len * zc, &st);
         if (!tabs) return st;
-        work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len * (zc + 1), &st);
+        work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len, &st);
         if (!work) return st;
     }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {

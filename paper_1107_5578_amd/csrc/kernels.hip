@@ -21,11 +21,13 @@
 //             and its reduction t - rint(t) are FP64, the sine/cosine FP32.
 //   Fresnel : H = C * Hx[p] * Hy[q]; the FFT of the sampled impulse response
 //             h_F factorises into two 1-D transforms of chirps, computed here
-//             in FP64 by direct summation.
+//             by FP64 FFTs.
 #include <cmath>
 #include <cstdlib>
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -296,10 +298,27 @@ struct FresnelH {
     }
 };
 
+// Work items of a persistent block. With G blocks and I items, both multiples of 8,
+// the blocks dispatched to XCD x (ids congruent to x mod 8) take the items of the
+// contiguous range [x*I/8, (x+1)*I/8) in turn, so neighbouring column tiles share
+// one L2; otherwise block b takes items b, b + G, ...
+struct ItemRange {
+    int first, step, end;
+};
+__device__ __forceinline__ ItemRange xcd_items(int bid, int nblocks, int items) {
+    if ((nblocks & 7) == 0 && (items & 7) == 0) {
+        const int per = items >> 3, x = bid & 7;
+        return ItemRange{x * per + (bid >> 3), nblocks >> 3, (x + 1) * per};
+    }
+    return ItemRange{bid, nblocks, items};
+}
+
+// Column pass: forward FFT of COLS columns, multiplication by the transfer function,
+// inverse FFT, in place; one (plane, column tile) item per block.
 template <int M, bool HALF, class HF, class ST>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_col(typename ST::E* __restrict__ buf,
-                                                              int ny, int mx, size_t plane, HF hf,
-                                                              float hscale,
+                                                              int ny, int mx, int batch,
+                                                              size_t plane, HF hf, float hscale,
                                                               const float2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int E = C::E, T = C::T, P = C::P;
@@ -309,13 +328,16 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     float2* lds = reinterpret_cast<float2*>(lds4);
     const int tid = threadIdx.x;
     const int pair = tid / T, j = tid % T;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int col0 = (blk * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
-    const bool active = col0 < mx;                 // blocks may overhang narrow planes
-    const int col = active ? col0 : 0;
-    SE* base = buf + blockIdx.y * plane + col;
+    float2* my_lds = lds + pair * C::LDS_PAIR;
     TwCache<M, E> twc;
     if constexpr (E == 16) twc.load(j, tw);
+    const int ntiles = (mx + C::COLS - 1) / C::COLS;
+    const int it = xcd_remap(blockIdx.x, gridDim.x);
+    const int pl = it / ntiles, tile = it - pl * ntiles;
+    const int col0 = (tile * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
+    const bool active = col0 < mx;                  // tiles may overhang narrow planes
+    const int col = active ? col0 : 0;
+    SE* base = buf + pl * plane + col;
     float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -330,7 +352,6 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
             for (int p = 0; p < P; ++p) v[p][r] = make_float2(0.f, 0.f);
         }
     }
-    float2* my_lds = lds + pair * C::LDS_PAIR;
     typename HF::Col hc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
@@ -364,12 +385,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
 // ---- z-stack column pass ------------------------------------------------------
 //
 // One field, many distances: the forward column transform is done once per column
-// pair and kept in registers; for each plane the spectrum is multiplied by that
-// plane's transfer function and inverse transformed into the plane's scratch.
+// and kept in registers; for each plane the spectrum is multiplied by that plane's
+// transfer function and inverse transformed into the plane's scratch.
 
 // The z-independent part of each bin is computed once, after the forward column
-// transform, and kept in a register across the plane loop; each plane then costs
-// one FP64 multiply and a reduction per bin.
+// transform, and kept across the plane loop; each plane then costs one FP64 multiply
+// and a reduction per bin.
 //
 // Fast form (every bin s <= 0.05): K = 1 - sqrt(1 - s) = s/2 + T(s) from the same
 // series as AsmHFast; the phase of plane z is zl - zl*K revolutions, i.e.
@@ -445,19 +466,26 @@ __device__ __forceinline__ void zcol_load(const float2* __restrict__ src, int ny
     }
 }
 
+// The z-stack planes are written column-major (element (y, x) of a plane at x*ny + y):
+// each column is contiguous, so a wavefront stores whole cache lines. Lines of these
+// planes are never read before they are written; row-major stores of single columns
+// would leave partially written lines in L2.
 template <int M, bool HALF>
-__device__ __forceinline__ void zcol_store(float2* __restrict__ dst, int ny, int mx, int j,
-                                           bool active, const float2 (&w)[1][ZColCfg<M>::E]) {
+__device__ __forceinline__ void zcol_store(float2* __restrict__ dst, int ny, int j, bool active,
+                                           const float2 (&w)[1][ZColCfg<M>::E]) {
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
         const bool st = active && (HALF ? (r < E / 2) : (y < ny));
-        if (st) dst[(size_t)y * mx] = w[0][r];
+        if (st) dst[y] = w[0][r];
     }
 }
 
+// The per-bin factor K of the thread's column is parked in LDS (each thread reads back
+// only what it wrote, so no barrier is involved): registers hold the forward spectrum
+// and the twiddles, which would not fit beside K at two waves per SIMD.
 template <int M, bool HALF, class ZH>
 __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
     const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
@@ -465,6 +493,7 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
     __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
+    __shared__ double kbl[C::PAIRS * M];
     const int tid = threadIdx.x;
     const int sub = tid / T, j = tid % T;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -472,22 +501,29 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
     const bool active = col0 < mx;
     const int col = active ? col0 : 0;
     float2* my_lds = lds + sub * C::LDS_PAIR;
+    double* my_kb = kbl + sub * M;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
     float2 v[1][E];
     zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    fft<M, E, 1, FWD>(v, my_lds, j, tw);
-    double kb[E];
+    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
+    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
 #pragma unroll
-    for (int r = 0; r < E; ++r) kb[r] = zs.h.bin(col, j + r * T);
+    for (int r = 0; r < E; ++r) my_kb[j + r * T] = zs.h.bin(col, j + r * T);
     for (int k = 0; k < zs.nz; ++k) {
-        const float2* twk = tw;  // opaque per plane: twiddles are reloaded, not kept live
-        asm volatile("" : "+s"(twk));
         const double zl = zs.zl[k];
         const float c0 = (float)(zl - rint(zl));
         float2 w[1][E];
 #pragma unroll
-        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(kb[r], zl, c0));
-        fft<M, E, 1, INV>(w, my_lds, j, twk);
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + col, ny, mx, j, active, w);
+        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(my_kb[j + r * T], zl, c0));
+        if constexpr (E == 16) {
+            fft<M, E, 1, INV>(w, my_lds, j, twc);
+        } else {
+            const float2* twk = tw;  // opaque per plane: twiddles are reloaded, not kept live
+            asm volatile("" : "+s"(twk));
+            fft<M, E, 1, INV>(w, my_lds, j, twk);
+        }
+        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
     }
 }
 
@@ -505,19 +541,26 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
     const bool active = col0 < mx;
     const int col = active ? col0 : 0;
     float2* my_lds = lds + sub * C::LDS_PAIR;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
     float2 v[1][E];
     zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
+    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
     for (int k = 0; k < zs.nz; ++k) {
-        const float2* twk = tw;
-        asm volatile("" : "+s"(twk));
         const float2* hk = zs.h + (size_t)k * zs.stride;
         const float2 hx = hk[col];
         float2 w[1][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], cmul(hx, hk[zs.mx + j + r * T]));
-        fft<M, E, 1, INV>(w, my_lds, j, twk);
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + col, ny, mx, j, active, w);
+        if constexpr (E == 16) {
+            fft<M, E, 1, INV>(w, my_lds, j, twc);
+        } else {
+            const float2* twk = tw;
+            asm volatile("" : "+s"(twk));
+            fft<M, E, 1, INV>(w, my_lds, j, twk);
+        }
+        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
     }
 }
 
@@ -614,6 +657,62 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv_pf(
         }
 #pragma unroll
         for (int r = 0; r < E; ++r) cur[r] = nxt[r];
+    }
+}
+
+// Row inverse of z-stack planes stored column-major (element (y, x) at x*ny + y, as the
+// z-stack column pass writes them). The data are laid out like the columns of the
+// column pass, so the same configuration applies: each thread transforms P adjacent
+// rows, reading P contiguous elements (16 bytes) per position; rows are stored to the
+// row-major outputs with the crop and the 1/(Mx*My) scale. Tiles of rows are taken in
+// XCD-contiguous ranges, so the blocks that share an input cache line share an L2.
+template <int M, bool HALF, class OUT>
+__global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_row_inv_t(
+    const float2* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
+    float scale, const float2* __restrict__ tw) {
+    using C = ColCfg<M>;
+    constexpr int E = C::E, T = C::T, P = C::P;
+    using PK = Pack<float2, P>;
+    __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
+    float2* lds = reinterpret_cast<float2*>(lds4);
+    const int tid = threadIdx.x;
+    const int pair = tid / T, j = tid % T;
+    float2* my_lds = lds + pair * C::LDS_PAIR;
+    TwCache<M, E> twc;
+    if constexpr (E == 16) twc.load(j, tw);
+    const int ntiles = (ny + C::COLS - 1) / C::COLS;
+    auto item = [&](int it) {
+        const int pl = it / ntiles, tile = it - pl * ntiles;
+        const int y0 = (tile * C::PAIRS + pair) * P;  // first row of this thread (ny is even)
+        const bool active = y0 < ny;
+        const float2* base = in + pl * in_plane + (active ? y0 : 0);
+        float2 v[P][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const PK t = *reinterpret_cast<const PK*>(base + (size_t)(j + r * T) * ny);
+#pragma unroll
+            for (int p = 0; p < P; ++p) v[p][r] = t.e[p];
+        }
+        if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
+        else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
+        if (active) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                float2* dst = outs(pl) + (size_t)(y0 + p) * nx;
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int x = j + r * T;
+                    if (HALF ? (r < E / 2) : (x < nx))
+                        dst[x] = make_float2(v[p][r].x * scale, v[p][r].y * scale);
+                }
+            }
+        }
+    };
+    if constexpr (HALF && E == 16) {
+        const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, ntiles * batch);
+        for (int it = ir.first; it < ir.end; it += ir.step) item(it);
+    } else {
+        item(xcd_remap(blockIdx.x, gridDim.x));
     }
 }
 
@@ -748,27 +847,8 @@ __global__ void k_twiddles(float2* tw, int m) {
 // ---- Fresnel transfer-function factors ---------------------------------------
 //
 // The FFT of the sampled impulse response h_F(m, n) = hx(m) hy(n) is the outer
-// product of two 1-D transforms, each computed here in FP64 by direct summation
-// with an FP64 twiddle table (index (p*d) mod M, so every twiddle is exact to an ulp).
-
-// chirp[k][i]: axis x for i < mx (d = i), axis y for i >= mx (d = i - mx);
-// h[d] = exp(i*pi*(s(d)*pitch)^2/(lambda z_k)) with s(d) = d for d < n, d - m otherwise.
-// The phase in revolutions, (s(d) pitch)^2 / (2 lambda z_k), is reduced in FP64.
-__global__ void k_chirps(double2* chirp, FresnelPlanes fp) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    const int len = fp.mx + fp.my;
-    if (i >= len) return;
-    const bool xa = i < fp.mx;
-    const int d = xa ? i : i - fp.mx;
-    const int m = xa ? fp.mx : fp.my, n = xa ? fp.nx : fp.ny;
-    const double off = (double)(d < n ? d : d - m) * (xa ? fp.dx : fp.dy);
-    const double t = fp.inv2lz[k] * (off * off);
-    const double r = t - rint(t);
-    double sn, cs;
-    sincospi(2.0 * r, &sn, &cs);
-    chirp[(size_t)k * len + i] = make_double2(cs, sn);
-}
+// product of two 1-D transforms, each computed here by an FP64 FFT with an FP64
+// twiddle table (every twiddle correct to an ulp).
 
 // tw64[i] = exp(-2*pi*i*d/m) for the x axis (i < mx) then the y axis
 __global__ void k_twiddles64(double2* tw, int mx, int my) {
@@ -781,39 +861,48 @@ __global__ void k_twiddles64(double2* tw, int mx, int my) {
     tw[i] = make_double2(cs, -sn);
 }
 
-// out[k][i] = coef * sum_d chirp[k][d] * tw[(p*d) mod m], one block of 256 threads per
-// output bin (axis x carries C_k, axis y carries 1).
-__global__ __launch_bounds__(256) void k_chirp_dft(const double2* __restrict__ chirp,
-                                                   const double2* __restrict__ tw64,
+// One 1-D Fresnel factor per block (blockIdx.x = axis, blockIdx.y = plane): the sampled
+// chirp h(d) = exp(i*pi*(s(d)*pitch)^2/(lambda z)) with signed offsets s(d), its length-m
+// DFT in FP64 (radix-2, decimation in time from bit-reversed order, in LDS), times the
+// plane constant C_k on the x axis, rounded to complex64. The chirp phase is reduced
+// modulo one revolution in FP64 before the sine and cosine.
+constexpr int kChirpMaxM = 8192;
+__global__ __launch_bounds__(256) void k_chirp_fft(const double2* __restrict__ tw64,
                                                    float2* __restrict__ out, FresnelPlanes fp) {
-    __shared__ double red[2][256];
-    const int i = blockIdx.x, k = blockIdx.y;
-    const int len = fp.mx + fp.my;
-    const bool xa = i < fp.mx;
-    const int p = xa ? i : i - fp.mx, m = xa ? fp.mx : fp.my;
-    const double2* h = chirp + (size_t)k * len + (xa ? 0 : fp.mx);
+    __shared__ double2 a[kChirpMaxM];
+    const bool xa = blockIdx.x == 0;
+    const int k = blockIdx.y;
+    const int m = xa ? fp.mx : fp.my, n = xa ? fp.nx : fp.ny;
+    const double pitch = xa ? fp.dx : fp.dy;
     const double2* w = tw64 + (xa ? 0 : fp.mx);
-    double ar = 0.0, ai = 0.0;
-    for (int d = threadIdx.x; d < m; d += 256) {
-        const double2 wd = w[(int)(((long long)p * d) & (m - 1))];
-        const double2 x = h[d];
-        ar += x.x * wd.x - x.y * wd.y;
-        ai += x.x * wd.y + x.y * wd.x;
+    const int lg = 31 - __clz(m);
+    for (int d = threadIdx.x; d < m; d += blockDim.x) {
+        const double off = (double)(d < n ? d : d - m) * pitch;
+        const double t = fp.inv2lz[k] * (off * off);
+        const double r = t - rint(t);
+        double sn, cs;
+        sincospi(2.0 * r, &sn, &cs);
+        a[__brev((unsigned)d) >> (32 - lg)] = make_double2(cs, sn);
     }
-    red[0][threadIdx.x] = ar;
-    red[1][threadIdx.x] = ai;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + st];
-            red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    for (int half = 1; half < m; half <<= 1) {
+        const int step = m / (2 * half);  // W_{2 half}^pos = W_m^(pos*step)
+        for (int t = threadIdx.x; t < m / 2; t += blockDim.x) {
+            const int pos = t & (half - 1);
+            const int i = 2 * (t - pos) + pos;
+            const double2 wv = w[pos * step];
+            const double2 x = a[i], y = a[i + half];
+            const double yr = y.x * wv.x - y.y * wv.y, yi = y.x * wv.y + y.y * wv.x;
+            a[i] = make_double2(x.x + yr, x.y + yi);
+            a[i + half] = make_double2(x.x - yr, x.y - yi);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double sr = red[0][0], si = red[1][0];
-        const double cr = xa ? fp.cre[k] : 1.0, ci = xa ? fp.cim[k] : 0.0;
-        out[(size_t)k * len + i] = make_float2((float)(sr * cr - si * ci), (float)(sr * ci + si * cr));
+    const double cr = xa ? fp.cre[k] : 1.0, ci = xa ? fp.cim[k] : 0.0;
+    float2* o = out + (size_t)k * (fp.mx + fp.my) + (xa ? 0 : fp.mx);
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+        const double2 v = a[p];
+        o[p] = make_float2((float)(v.x * cr - v.y * ci), (float)(v.x * ci + v.y * cr));
     }
 }
 
@@ -839,17 +928,33 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Blocks of a persistent kernel that are resident at once on the current device (at
+// most `items`). The occupancy query is answered once per kernel and device.
 template <class K>
 static int resident_blocks(K kernel, int threads, int items) {
-    int dev = 0, cus = 0, occ = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-        cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess ||
-        occ <= 0)
-        occ = 1;
-    const long long n = (long long)occ * cus;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, long long> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+    long long n = 0;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) n = it->second;
+    }
+    if (n == 0) {
+        int cus = 0, occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess ||
+            occ <= 0)
+            occ = 1;
+        n = (long long)occ * cus;
+        std::lock_guard<std::mutex> g(mu);
+        cache[key] = n;
+    }
     return (int)(items < n ? items : n);
 }
 
@@ -912,15 +1017,16 @@ static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, siz
     using SE = typename ST::E;
     CWO_DISPATCH_M(my, {
         using C = ColCfg<MM>;
-        dim3 grid((mx + C::COLS - 1) / C::COLS, batch);
-        if (half)
-            hipLaunchKernelGGL((k_col<MM, true, HF, ST>), grid, dim3(C::THREADS), 0, s, (SE*)buf,
-                               ny, mx, plane, hf, hscale, tw);
-        else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_col<MM, false, HF, ST>), grid, dim3(C::THREADS), 0, s, (SE*)buf,
-                               ny, mx, plane, hf, hscale, tw);
-        else
+        const int items = (mx + C::COLS - 1) / C::COLS * batch;
+        if (half) {
+            hipLaunchKernelGGL((k_col<MM, true, HF, ST>), dim3(items), dim3(C::THREADS), 0, s,
+                               (SE*)buf, ny, mx, batch, plane, hf, hscale, tw);
+        } else if constexpr (std::is_same_v<ST, StF32>) {
+            hipLaunchKernelGGL((k_col<MM, false, HF, ST>), dim3(items), dim3(C::THREADS), 0, s,
+                               (SE*)buf, ny, mx, batch, plane, hf, hscale, tw);
+        } else {
             return hipErrorInvalidValue;
+        }
     });
     return hipGetLastError();
 }
@@ -1095,7 +1201,21 @@ hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny
                             size_t zplane, float scale, const float2* tw, hipStream_t s) {
     OutTable t;
     for (int k = 0; k < kZChunk; ++k) t.out[k] = k < zc.nz ? zc.out[k] : nullptr;
-    return launch_row_inv_impl(zbuf, t, nx, ny, mx, zc.nz, zplane, scale, tw, s);
+    const bool half = (mx == 2 * nx);
+    CWO_DISPATCH_M(mx, {
+        using C = ColCfg<MM>;
+        const int items = (ny + C::COLS - 1) / C::COLS * zc.nz;
+        if (half) {
+            auto k = k_row_inv_t<MM, true, OutTable>;
+            const int g = C::E == 16 ? resident_blocks(k, C::THREADS, items) : items;
+            hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, zbuf, t, nx, ny, zc.nz, zplane,
+                               scale, tw);
+        } else {
+            hipLaunchKernelGGL((k_row_inv_t<MM, false, OutTable>), dim3(items), dim3(C::THREADS),
+                               0, s, zbuf, t, nx, ny, zc.nz, zplane, scale, tw);
+        }
+    });
+    return hipGetLastError();
 }
 
 template <class ZH>
@@ -1178,13 +1298,11 @@ hipError_t launch_gs_errors(const double* num, const float* amp, double* den_wor
 
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s) {
+    if (fp.mx > kChirpMaxM || fp.my > kChirpMaxM) return hipErrorInvalidValue;
     const int len = fp.mx + fp.my;
-    double2* chirp = work;
-    double2* tw64 = work + (size_t)len * fp.nz;
+    double2* tw64 = work;
     hipLaunchKernelGGL(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);
-    hipLaunchKernelGGL(k_chirps, dim3((len + 255) / 256, fp.nz), dim3(256), 0, s, chirp, fp);
-    hipLaunchKernelGGL(k_chirp_dft, dim3(len, fp.nz), dim3(256), 0, s, (const double2*)chirp,
-                       (const double2*)tw64, out, fp);
+    hipLaunchKernelGGL(k_chirp_fft, dim3(2, fp.nz), dim3(256), 0, s, (const double2*)tw64, out, fp);
     return hipGetLastError();
 }
 

@@ -110,7 +110,7 @@ struct FresnelPlanes {
     double inv2lz[kZChunk];       // 1 / (2 lambda z_k): chirp phase in revolutions per m^2
     double cre[kZChunk], cim[kZChunk];  // C_k = dx dy exp(i k z_k) / (i lambda z_k)
 };
-// work must hold (mx + my) * (nz + 1) double2 (chirps, then the FP64 twiddle tables).
+// work must hold mx + my double2 (the FP64 twiddle tables); mx, my <= 8192.
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s);
 

@@ -85,6 +85,25 @@ def test_zstack_sizes(ctx, kind, n, ny):
         check(stack[k].cpu().numpy(), ref, "zstack-%s-%dx%d plane %d" % (kind, n, ny, k))
 
 
+@pytest.mark.parametrize("kind", ["asm", "fresnel"])
+def test_zstack_4096(ctx, kind):
+    # padded length 8192: the longest transforms (32 values per thread), the largest
+    # z-stack LDS footprint and the largest FP64 chirp transforms
+    import torch
+    n = 4096
+    u = W.uniform_random_field(n, 4096 + (kind == "fresnel"))
+    zs = [0.35, -0.6]
+    note("zstack %s %dx%d nz=%d" % (kind, n, n, len(zs)))
+    t = torch.from_numpy(u).cuda()
+    stack = ctx.zstack(t, zs, 8e-6, 8e-6, 532e-9, kind=kind)
+    torch.cuda.synchronize()
+    for k, z in enumerate(zs):
+        one = single(ctx, kind, t, 8e-6, 532e-9, z).cpu().numpy()
+        assert D.rel_l2(stack[k].cpu().numpy(), one.astype(np.complex128)) <= 1e-6
+    ref = D.propagate(u, kind, 8e-6, 8e-6, 532e-9, zs[1])
+    check(stack[1].cpu().numpy(), ref, "zstack-%s-4096 plane 1" % kind)
+
+
 def test_zstack_exact_phase_path(ctx):
     # 0.6 um pitch at 633 nm: s reaches 2*(lambda/2dx)^2 = 0.56 > 0.05, so the stack takes
     # the exact per-bin FP64 form (and evanescent bins appear at the corners)
