@@ -22,77 +22,10 @@
 //   Fresnel : H = C * Hx[p] * Hy[q]; the FFT of the sampled impulse response
 //             h_F factorises into two 1-D transforms of chirps, computed here
 //             by FP64 FFTs.
-#include <cmath>
-#include <cstdlib>
-#include <cstddef>
-#include <cstdint>
-#include <map>
-#include <mutex>
-#include <type_traits>
-#include <utility>
 
-#include "fft_device.hpp"
-#include "launch.hpp"
+#include "kernel_common.hpp"
 
 namespace cwo {
-
-// ---- configuration per transform length --------------------------------------
-
-// Row passes: one transform per thread group of T = M/E threads, RPB rows per block.
-template <int M>
-struct RowCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
-    static constexpr int T = M / E;
-    static constexpr int RPB = (T >= 256) ? 1 : 256 / T;  // rows per block
-    static constexpr int THREADS = T * RPB;
-};
-
-// Column pass: each thread transforms two adjacent columns (16-byte loads and
-// stores, one 16-byte LDS slot per element pair); PAIRS column pairs per block.
-template <int M>
-struct ColCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
-    static constexpr int T = M / E;
-    // two columns per thread, except at M = 8192 where 32 values per column already
-    // fill the register budget; the two columns share one LDS buffer (split exchange)
-    static constexpr int P = (M == 8192) ? 1 : 2;
-    static constexpr bool SPLIT = false;
-    static constexpr int LDS_PAIR = (SPLIT ? 1 : P) * lds_elems<M>();  // float2 entries per pair
-    static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
-    static constexpr int BY_LDS0 = (72 * 1024) / (LDS_PAIR * 8);
-    static constexpr int BY_LDS = BY_LDS0 < 1 ? 1 : BY_LDS0;
-    static constexpr int PAIRS0 = BY_THR < BY_LDS ? BY_THR : BY_LDS;
-    static constexpr int PAIRS = PAIRS0 > 16 ? 16 : PAIRS0;
-    static constexpr int THREADS = T * PAIRS;
-    static constexpr int COLS = P * PAIRS;  // columns per block
-    static constexpr int WAVES_PER_EU = 2;
-};
-
-// z-stack column pass: the forward spectrum stays in registers while each plane's
-// inverse transform runs on a copy, so one column per thread.
-template <int M>
-struct ZColCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
-    static constexpr int T = M / E;
-    static constexpr int P = 1;
-    static constexpr int LDS_PAIR = lds_elems<M>();
-    static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
-    static constexpr int BY_LDS0 = (72 * 1024) / (LDS_PAIR * 8);
-    static constexpr int BY_LDS = BY_LDS0 < 1 ? 1 : BY_LDS0;
-    static constexpr int PAIRS0 = BY_THR < BY_LDS ? BY_THR : BY_LDS;
-    static constexpr int PAIRS = PAIRS0 > 16 ? 16 : PAIRS0;
-    static constexpr int THREADS = T * PAIRS;
-    static constexpr int COLS = P * PAIRS;
-};
-
-// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs, which
-// have separate L2 caches. Remap so that each XCD works on a contiguous range
-// of tiles; neighbouring tiles share cache lines.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-    if ((nblocks & 7) != 0) return bid;
-    const int per = nblocks >> 3;
-    return (bid & 7) * per + (bid >> 3);
-}
 
 // ---- row forward: zero-pad + FFT --------------------------------------------
 
@@ -298,21 +231,6 @@ struct FresnelH {
     }
 };
 
-// Work items of a persistent block. With G blocks and I items, both multiples of 8,
-// the blocks dispatched to XCD x (ids congruent to x mod 8) take the items of the
-// contiguous range [x*I/8, (x+1)*I/8) in turn, so neighbouring column tiles share
-// one L2; otherwise block b takes items b, b + G, ...
-struct ItemRange {
-    int first, step, end;
-};
-__device__ __forceinline__ ItemRange xcd_items(int bid, int nblocks, int items) {
-    if ((nblocks & 7) == 0 && (items & 7) == 0) {
-        const int per = items >> 3, x = bid & 7;
-        return ItemRange{x * per + (bid >> 3), nblocks >> 3, (x + 1) * per};
-    }
-    return ItemRange{bid, nblocks, items};
-}
-
 // Column pass: forward FFT of COLS columns, multiplication by the transfer function,
 // inverse FFT, in place; one (plane, column tile) item per block.
 template <int M, bool HALF, class HF, class ST>
@@ -382,199 +300,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     }
 }
 
-// ---- z-stack column pass ------------------------------------------------------
-//
-// One field, many distances: the forward column transform is done once per column
-// and kept in registers; for each plane the spectrum is multiplied by that plane's
-// transfer function and inverse transformed into the plane's scratch.
-
-// The z-independent part of each bin is computed once, after the forward column
-// transform, and kept across the plane loop; each plane then costs one FP64 multiply
-// and a reduction per bin.
-//
-// Fast form (every bin s <= 0.05): K = 1 - sqrt(1 - s) = s/2 + T(s) from the same
-// series as AsmHFast; the phase of plane z is zl - zl*K revolutions, i.e.
-// reduce(zl) - reduce(zl*K). Exact form: Q = sqrt(1 - s) in FP64 (Q < 0 marks an
-// evanescent bin, s > 1, decided with the reference's operations); the phase is zl*Q.
-struct AsmZFast {
-    double lam_dfx, lam_dfy;
-    int mx, my;
-    __device__ __forceinline__ double bin(int p, int q) const {
-        const double x = (double)(p < mx / 2 ? p : p - mx) * lam_dfx;
-        const double y = (double)(q < my / 2 ? q : q - my) * lam_dfy;
-        const double s = x * x + y * y;
-        double poly = 715.0 / 65536.0;
-        poly = fma(poly, s, 429.0 / 32768.0);
-        poly = fma(poly, s, 33.0 / 2048.0);
-        poly = fma(poly, s, 21.0 / 1024.0);
-        poly = fma(poly, s, 7.0 / 256.0);
-        poly = fma(poly, s, 5.0 / 128.0);
-        poly = fma(poly, s, 1.0 / 16.0);
-        poly = fma(poly, s, 1.0 / 8.0);
-        return fma(s * s, poly, 0.5 * s);
-    }
-    __device__ __forceinline__ float2 at(double k, double zl, float c0) const {
-        const double u = zl * k;
-        float r = c0 - (float)(u - rint(u));
-        r -= rintf(r);
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    }
-};
-
-struct AsmZExact {
-    double dfx, dfy, lam;
-    int mx, my;
-    __device__ __forceinline__ double bin(int p, int q) const {
-        const double pp = (double)(p < mx / 2 ? p : p - mx);
-        const double qq = (double)(q < my / 2 ? q : q - my);
-        const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
-        const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
-        const double s = __dadd_rn(__dmul_rn(ay, ay), __dmul_rn(ax, ax));
-        return (s <= 1.0) ? __dsqrt_rn(1.0 - s) : -1.0;
-    }
-    __device__ __forceinline__ float2 at(double qv, double zl, float) const {
-        if (qv < 0.0) return make_float2(0.f, 0.f);
-        const double t = zl * qv;
-        const float r = (float)(t - rint(t));
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    }
-};
-
-template <class ZH>
-struct ZSetAsm {
-    ZH h;
-    double zl[kZChunk];
-    int nz;
-};
-
-struct ZSetFresnel {
-    const float2* h;  // plane k: Hx (with C) at h + k*stride, Hy at h + k*stride + mx
-    size_t stride;
-    int mx, nz;
-};
-
-template <int M, bool HALF>
-__device__ __forceinline__ void zcol_load(const float2* __restrict__ src, int ny, int mx, int j,
-                                          bool active, float2 (&v)[1][ZColCfg<M>::E]) {
-    using C = ZColCfg<M>;
-    constexpr int E = C::E, T = C::T;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int y = j + r * T;
-        const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
-        v[0][r] = ld ? src[(size_t)y * mx] : make_float2(0.f, 0.f);
-    }
-}
-
-// The z-stack planes are written column-major (element (y, x) of a plane at x*ny + y):
-// each column is contiguous, so a wavefront stores whole cache lines. Lines of these
-// planes are never read before they are written; row-major stores of single columns
-// would leave partially written lines in L2.
-template <int M, bool HALF>
-__device__ __forceinline__ void zcol_store(float2* __restrict__ dst, int ny, int j, bool active,
-                                           const float2 (&w)[1][ZColCfg<M>::E]) {
-    using C = ZColCfg<M>;
-    constexpr int E = C::E, T = C::T;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int y = j + r * T;
-        const bool st = active && (HALF ? (r < E / 2) : (y < ny));
-        if (st) dst[y] = w[0][r];
-    }
-}
-
-// The per-bin factor K of the thread's column is parked in LDS (each thread reads back
-// only what it wrote, so no barrier is involved): registers hold the forward spectrum
-// and the twiddles, which would not fit beside K at two waves per SIMD.
-template <int M, bool HALF, class ZH>
-__global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
-    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
-    ZSetAsm<ZH> zs, const float2* __restrict__ tw) {
-    using C = ZColCfg<M>;
-    constexpr int E = C::E, T = C::T;
-    __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
-    __shared__ double kbl[C::PAIRS * M];
-    const int tid = threadIdx.x;
-    const int sub = tid / T, j = tid % T;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int col0 = blk * C::PAIRS + sub;
-    const bool active = col0 < mx;
-    const int col = active ? col0 : 0;
-    float2* my_lds = lds + sub * C::LDS_PAIR;
-    double* my_kb = kbl + sub * M;
-    TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
-    float2 v[1][E];
-    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
-    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
-#pragma unroll
-    for (int r = 0; r < E; ++r) my_kb[j + r * T] = zs.h.bin(col, j + r * T);
-    for (int k = 0; k < zs.nz; ++k) {
-        const double zl = zs.zl[k];
-        const float c0 = (float)(zl - rint(zl));
-        float2 w[1][E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(my_kb[j + r * T], zl, c0));
-        if constexpr (E == 16) {
-            fft<M, E, 1, INV>(w, my_lds, j, twc);
-        } else {
-            const float2* twk = tw;  // opaque per plane: twiddles are reloaded, not kept live
-            asm volatile("" : "+s"(twk));
-            fft<M, E, 1, INV>(w, my_lds, j, twk);
-        }
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
-    }
-}
-
-template <int M, bool HALF>
-__global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
-    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
-    ZSetFresnel zs, const float2* __restrict__ tw) {
-    using C = ZColCfg<M>;
-    constexpr int E = C::E, T = C::T;
-    __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
-    const int tid = threadIdx.x;
-    const int sub = tid / T, j = tid % T;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int col0 = blk * C::PAIRS + sub;
-    const bool active = col0 < mx;
-    const int col = active ? col0 : 0;
-    float2* my_lds = lds + sub * C::LDS_PAIR;
-    TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
-    float2 v[1][E];
-    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
-    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
-    for (int k = 0; k < zs.nz; ++k) {
-        const float2* hk = zs.h + (size_t)k * zs.stride;
-        const float2 hx = hk[col];
-        float2 w[1][E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], cmul(hx, hk[zs.mx + j + r * T]));
-        if constexpr (E == 16) {
-            fft<M, E, 1, INV>(w, my_lds, j, twc);
-        } else {
-            const float2* twk = tw;
-            asm volatile("" : "+s"(twk));
-            fft<M, E, 1, INV>(w, my_lds, j, twk);
-        }
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
-    }
-}
-
 // ---- row inverse: IFFT + crop + normalisation ---------------------------------
-
-struct OutStrided {
-    float2* out;
-    size_t plane;
-    __device__ __forceinline__ float2* operator()(int k) const { return out + k * plane; }
-};
-struct OutTable {
-    float2* out[kZChunk];
-    __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
-};
 
 template <int M, bool HALF, class OUT, class ST>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
@@ -660,179 +386,6 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv_pf(
     }
 }
 
-// Row inverse of z-stack planes stored column-major (element (y, x) at x*ny + y, as the
-// z-stack column pass writes them). The data are laid out like the columns of the
-// column pass, so the same configuration applies: each thread transforms P adjacent
-// rows, reading P contiguous elements (16 bytes) per position; rows are stored to the
-// row-major outputs with the crop and the 1/(Mx*My) scale. Tiles of rows are taken in
-// XCD-contiguous ranges, so the blocks that share an input cache line share an L2.
-template <int M, bool HALF, class OUT>
-__global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_row_inv_t(
-    const float2* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
-    float scale, const float2* __restrict__ tw) {
-    using C = ColCfg<M>;
-    constexpr int E = C::E, T = C::T, P = C::P;
-    using PK = Pack<float2, P>;
-    __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
-    float2* lds = reinterpret_cast<float2*>(lds4);
-    const int tid = threadIdx.x;
-    const int pair = tid / T, j = tid % T;
-    float2* my_lds = lds + pair * C::LDS_PAIR;
-    TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
-    const int ntiles = (ny + C::COLS - 1) / C::COLS;
-    auto item = [&](int it) {
-        const int pl = it / ntiles, tile = it - pl * ntiles;
-        const int y0 = (tile * C::PAIRS + pair) * P;  // first row of this thread (ny is even)
-        const bool active = y0 < ny;
-        const float2* base = in + pl * in_plane + (active ? y0 : 0);
-        float2 v[P][E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const PK t = *reinterpret_cast<const PK*>(base + (size_t)(j + r * T) * ny);
-#pragma unroll
-            for (int p = 0; p < P; ++p) v[p][r] = t.e[p];
-        }
-        if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
-        else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
-        if (active) {
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                float2* dst = outs(pl) + (size_t)(y0 + p) * nx;
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    const int x = j + r * T;
-                    if (HALF ? (r < E / 2) : (x < nx))
-                        dst[x] = make_float2(v[p][r].x * scale, v[p][r].y * scale);
-                }
-            }
-        }
-    };
-    if constexpr (HALF && E == 16) {
-        const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, ntiles * batch);
-        for (int it = ir.first; it < ir.end; it += ir.step) item(it);
-    } else {
-        item(xcd_remap(blockIdx.x, gridDim.x));
-    }
-}
-
-// ---- ping-pong iteration row kernel ----------------------------------------------
-//
-// Row inverse transform, crop, amplitude constraint and re-padded forward transform
-// fused, so one propagation of the iteration is a column pass plus this kernel.
-
-template <int M, bool HALF>
-__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(float2* __restrict__ spec,
-                                                                 const float* __restrict__ amp,
-                                                                 float2* __restrict__ out,
-                                                                 double* __restrict__ num, int nx,
-                                                                 int ny, float scale,
-                                                                 const float2* __restrict__ tw) {
-    using C = RowCfg<M>;
-    constexpr int E = C::E, T = C::T;
-    __shared__ float2 lds[C::RPB * lds_elems<M>()];
-    const int tid = threadIdx.x;
-    const int sub = tid / T, j = tid % T;
-    const int row = blockIdx.x * C::RPB + sub;
-    const bool valid = row < ny;
-    float2* srow = spec + (size_t)(valid ? row : 0) * M;
-    const float* arow = amp + (size_t)(valid ? row : 0) * nx;
-    float2* my_lds = lds + sub * lds_elems<M>();
-    float2 v[1][E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) v[0][r] = valid ? srow[j + r * T] : make_float2(0.f, 0.f);
-    fft<M, E, 1, INV>(v, my_lds, j, tw);
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int x = j + r * T;
-        const bool in_field = HALF ? (r < E / 2) : (x < nx);
-        if (in_field) {
-            const float a = valid ? arow[x] : 0.f;
-            const float re = v[0][r].x * scale, im = v[0][r].y * scale;
-            const float m2 = re * re + im * im;
-            float2 c;
-            if (m2 > 0.f) {
-                const float mag = __fsqrt_rn(m2);
-                const float f = a / mag;
-                c = make_float2(re * f, im * f);
-                const double d = (double)mag - (double)a;
-                acc += d * d;
-            } else {
-                c = make_float2(a, 0.f);
-                acc += (double)a * (double)a;
-            }
-            v[0][r] = c;
-        } else {
-            v[0][r] = make_float2(0.f, 0.f);  // the padding of the next forward transform
-        }
-    }
-    if (num) {
-        // deterministic per-row sum: lane partials through LDS, summed in index order
-        double* red = reinterpret_cast<double*>(my_lds);
-        lds_barrier();
-        red[j] = acc;
-        lds_barrier();
-        if (j == 0 && valid) {
-            double t = 0.0;
-            for (int i = 0; i < T; ++i) t += red[i];
-            num[row] = t;
-        }
-        lds_barrier();
-    }
-    if (out) {
-        if (valid) {
-            float2* orow = out + (size_t)row * nx;
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const int x = j + r * T;
-                if (HALF ? (r < E / 2) : (x < nx)) orow[x] = v[0][r];
-            }
-        }
-        return;
-    }
-    fft<M, E, 1, FWD>(v, my_lds, j, tw);
-    if (valid) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) srow[j + r * T] = v[0][r];
-    }
-}
-
-// den = sum(amp^2) in FP64 by one block (deterministic order), then one block per
-// iteration sums its row partials.
-__global__ __launch_bounds__(256) void k_gs_den(const float* __restrict__ amp, double* den,
-                                                long long count) {
-    __shared__ double red[256];
-    double t = 0.0;
-    for (long long i = threadIdx.x; i < count; i += 256) {
-        const double a = amp[i];
-        t += a * a;
-    }
-    red[threadIdx.x] = t;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *den = red[0];
-}
-
-__global__ __launch_bounds__(256) void k_gs_errors(const double* __restrict__ num,
-                                                   const double* __restrict__ den,
-                                                   float* __restrict__ errors, int ny) {
-    __shared__ double red[256];
-    const int k = blockIdx.x;
-    double t = 0.0;
-    for (int i = threadIdx.x; i < ny; i += 256) t += num[(size_t)k * ny + i];
-    red[threadIdx.x] = t;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) errors[k] = (float)sqrt(red[0] / *den);
-}
-
 // ---- tables -------------------------------------------------------------------
 
 // tw[k] = exp(-2*pi*i*k/M), evaluated in FP64 and rounded once to FP32
@@ -844,118 +397,11 @@ __global__ void k_twiddles(float2* tw, int m) {
     tw[k] = make_float2((float)c, (float)(-s));
 }
 
-// ---- Fresnel transfer-function factors ---------------------------------------
-//
-// The FFT of the sampled impulse response h_F(m, n) = hx(m) hy(n) is the outer
-// product of two 1-D transforms, each computed here by an FP64 FFT with an FP64
-// twiddle table (every twiddle correct to an ulp).
-
-// tw64[i] = exp(-2*pi*i*d/m) for the x axis (i < mx) then the y axis
-__global__ void k_twiddles64(double2* tw, int mx, int my) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= mx + my) return;
-    const bool xa = i < mx;
-    const int d = xa ? i : i - mx, m = xa ? mx : my;
-    double sn, cs;
-    sincospi(2.0 * (double)d / (double)m, &sn, &cs);
-    tw[i] = make_double2(cs, -sn);
-}
-
-// One 1-D Fresnel factor per block (blockIdx.x = axis, blockIdx.y = plane): the sampled
-// chirp h(d) = exp(i*pi*(s(d)*pitch)^2/(lambda z)) with signed offsets s(d), its length-m
-// DFT in FP64 (radix-2, decimation in time from bit-reversed order, in LDS), times the
-// plane constant C_k on the x axis, rounded to complex64. The chirp phase is reduced
-// modulo one revolution in FP64 before the sine and cosine.
-constexpr int kChirpMaxM = 8192;
-__global__ __launch_bounds__(256) void k_chirp_fft(const double2* __restrict__ tw64,
-                                                   float2* __restrict__ out, FresnelPlanes fp) {
-    __shared__ double2 a[kChirpMaxM];
-    const bool xa = blockIdx.x == 0;
-    const int k = blockIdx.y;
-    const int m = xa ? fp.mx : fp.my, n = xa ? fp.nx : fp.ny;
-    const double pitch = xa ? fp.dx : fp.dy;
-    const double2* w = tw64 + (xa ? 0 : fp.mx);
-    const int lg = 31 - __clz(m);
-    for (int d = threadIdx.x; d < m; d += blockDim.x) {
-        const double off = (double)(d < n ? d : d - m) * pitch;
-        const double t = fp.inv2lz[k] * (off * off);
-        const double r = t - rint(t);
-        double sn, cs;
-        sincospi(2.0 * r, &sn, &cs);
-        a[__brev((unsigned)d) >> (32 - lg)] = make_double2(cs, sn);
-    }
-    __syncthreads();
-    for (int half = 1; half < m; half <<= 1) {
-        const int step = m / (2 * half);  // W_{2 half}^pos = W_m^(pos*step)
-        for (int t = threadIdx.x; t < m / 2; t += blockDim.x) {
-            const int pos = t & (half - 1);
-            const int i = 2 * (t - pos) + pos;
-            const double2 wv = w[pos * step];
-            const double2 x = a[i], y = a[i + half];
-            const double yr = y.x * wv.x - y.y * wv.y, yi = y.x * wv.y + y.y * wv.x;
-            a[i] = make_double2(x.x + yr, x.y + yi);
-            a[i + half] = make_double2(x.x - yr, x.y - yi);
-        }
-        __syncthreads();
-    }
-    const double cr = xa ? fp.cre[k] : 1.0, ci = xa ? fp.cim[k] : 0.0;
-    float2* o = out + (size_t)k * (fp.mx + fp.my) + (xa ? 0 : fp.mx);
-    for (int p = threadIdx.x; p < m; p += blockDim.x) {
-        const double2 v = a[p];
-        o[p] = make_float2((float)(v.x * cr - v.y * ci), (float)(v.x * ci + v.y * cr));
-    }
-}
-
 // ---- host launchers ------------------------------------------------------------
-
-#define CWO_DISPATCH_M(M_, ...)              \
-    switch (M_) {                             \
-        case 16: { constexpr int MM = 16; __VA_ARGS__; } break;     \
-        case 32: { constexpr int MM = 32; __VA_ARGS__; } break;     \
-        case 64: { constexpr int MM = 64; __VA_ARGS__; } break;     \
-        case 128: { constexpr int MM = 128; __VA_ARGS__; } break;   \
-        case 256: { constexpr int MM = 256; __VA_ARGS__; } break;   \
-        case 512: { constexpr int MM = 512; __VA_ARGS__; } break;   \
-        case 1024: { constexpr int MM = 1024; __VA_ARGS__; } break; \
-        case 2048: { constexpr int MM = 2048; __VA_ARGS__; } break; \
-        case 4096: { constexpr int MM = 4096; __VA_ARGS__; } break; \
-        case 8192: { constexpr int MM = 8192; __VA_ARGS__; } break; \
-        default: return hipErrorInvalidValue;                 \
-    }
 
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
     hipLaunchKernelGGL(k_twiddles, dim3((m + 255) / 256), dim3(256), 0, s, tw, m);
     return hipGetLastError();
-}
-
-// Blocks of a persistent kernel that are resident at once on the current device (at
-// most `items`). The occupancy query is answered once per kernel and device.
-template <class K>
-static int resident_blocks(K kernel, int threads, int items) {
-    static std::mutex mu;
-    static std::map<std::pair<const void*, int>, long long> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
-    long long n = 0;
-    {
-        std::lock_guard<std::mutex> g(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) n = it->second;
-    }
-    if (n == 0) {
-        int cus = 0, occ = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess ||
-            occ <= 0)
-            occ = 1;
-        n = (long long)occ * cus;
-        std::lock_guard<std::mutex> g(mu);
-        cache[key] = n;
-    }
-    return (int)(items < n ? items : n);
 }
 
 template <class ST>
@@ -1194,115 +640,6 @@ hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream
     const int nb = blocks < 1 ? 1 : blocks;
     hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, s, in, n, work + 2);
     hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, (const float*)(work + 2), nb, work);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
-                            size_t zplane, float scale, const float2* tw, hipStream_t s) {
-    OutTable t;
-    for (int k = 0; k < kZChunk; ++k) t.out[k] = k < zc.nz ? zc.out[k] : nullptr;
-    const bool half = (mx == 2 * nx);
-    CWO_DISPATCH_M(mx, {
-        using C = ColCfg<MM>;
-        const int items = (ny + C::COLS - 1) / C::COLS * zc.nz;
-        if (half) {
-            auto k = k_row_inv_t<MM, true, OutTable>;
-            const int g = C::E == 16 ? resident_blocks(k, C::THREADS, items) : items;
-            hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, zbuf, t, nx, ny, zc.nz, zplane,
-                               scale, tw);
-        } else {
-            hipLaunchKernelGGL((k_row_inv_t<MM, false, OutTable>), dim3(items), dim3(C::THREADS),
-                               0, s, zbuf, t, nx, ny, zc.nz, zplane, scale, tw);
-        }
-    });
-    return hipGetLastError();
-}
-
-template <class ZH>
-static hipError_t launch_col_z_asm_impl(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                                        size_t zplane, const ZSetAsm<ZH>& zs, const float2* tw,
-                                        hipStream_t s) {
-    const bool half = (my == 2 * ny);
-    CWO_DISPATCH_M(my, {
-        using C = ZColCfg<MM>;
-        dim3 grid((mx + C::COLS - 1) / C::COLS);
-        if (half)
-            hipLaunchKernelGGL((k_col_z_asm<MM, true, ZH>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-        else
-            hipLaunchKernelGGL((k_col_z_asm<MM, false, ZH>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                            size_t zplane, const AsmScalars& a, const ZChunk& zc,
-                            const float2* tw, hipStream_t s) {
-    const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
-    if (sx * sx + sy * sy <= kAsmFastMaxS) {
-        ZSetAsm<AsmZFast> zs;
-        zs.h = AsmZFast{a.lam * a.dfx, a.lam * a.dfy, mx, my};
-        for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
-        zs.nz = zc.nz;
-        return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
-    }
-    ZSetAsm<AsmZExact> zs;
-    zs.h = AsmZExact{a.dfx, a.dfy, a.lam, mx, my};
-    for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
-    zs.nz = zc.nz;
-    return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
-}
-
-hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                                size_t zplane, const float2* h, int nz, const float2* tw,
-                                hipStream_t s) {
-    ZSetFresnel zs{h, (size_t)(mx + my), mx, nz};
-    const bool half = (my == 2 * ny);
-    CWO_DISPATCH_M(my, {
-        using C = ZColCfg<MM>;
-        dim3 grid((mx + C::COLS - 1) / C::COLS);
-        if (half)
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, true>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-        else
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, false>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_row_gs(float2* spec, const float* amp, float2* out, double* num, int nx, int ny,
-                         int mx, float scale, const float2* tw, hipStream_t s) {
-    const bool half = (mx == 2 * nx);
-    CWO_DISPATCH_M(mx, {
-        using C = RowCfg<MM>;
-        dim3 grid((ny + C::RPB - 1) / C::RPB);
-        if (half)
-            hipLaunchKernelGGL((k_row_gs<MM, true>), grid, dim3(C::THREADS), 0, s, spec, amp, out,
-                               num, nx, ny, scale, tw);
-        else
-            hipLaunchKernelGGL((k_row_gs<MM, false>), grid, dim3(C::THREADS), 0, s, spec, amp, out,
-                               num, nx, ny, scale, tw);
-    });
-    return hipGetLastError();
-}
-
-hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
-                            int nx, int ny, int iters, hipStream_t s) {
-    hipLaunchKernelGGL(k_gs_den, dim3(1), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
-    hipLaunchKernelGGL(k_gs_errors, dim3(iters), dim3(256), 0, s, num, (const double*)den_work,
-                       errors, ny);
-    return hipGetLastError();
-}
-
-hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
-                                 hipStream_t s) {
-    if (fp.mx > kChirpMaxM || fp.my > kChirpMaxM) return hipErrorInvalidValue;
-    const int len = fp.mx + fp.my;
-    double2* tw64 = work;
-    hipLaunchKernelGGL(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);
-    hipLaunchKernelGGL(k_chirp_fft, dim3(2, fp.nz), dim3(256), 0, s, (const double2*)tw64, out, fp);
     return hipGetLastError();
 }
 
