@@ -14,7 +14,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/cwo.h"
+#include "cwo.h"
 #include "launch.hpp"
 
 namespace {
