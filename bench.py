@@ -38,7 +38,8 @@ def stage_bytes(n: int, elem: int = 8) -> dict:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_1107_5578_amd/csrc/plane.hip", "paper_1107_5578_amd/csrc/kernel_common.hpp",
+    for rel in ("paper_1107_5578_amd/csrc/plane.hip", "paper_1107_5578_amd/csrc/column.hpp",
+                "paper_1107_5578_amd/csrc/kernel_common.hpp",
                 "paper_1107_5578_amd/csrc/fft_device.hpp", "paper_1107_5578_amd/csrc/launch.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())

@@ -108,6 +108,30 @@ cwo_status cwo_asm(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
 cwo_status cwo_fresnel(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
                        void* hip_stream);
 
+/* Shifted angular spectrum method (Sec. 2.1.5, Eqs. shift_ang1 and shift_ang2): the
+ * transfer function of cwo_asm times exp(i 2 pi (ox fx + oy fy)) and times the band-limit
+ * functions Rect((fx - cx)/wx) Rect((fy - cy)/wy), Rect(t) = 1 for |t| <= 1/2. The linear
+ * phase moves the destination window: output sample (m, n) lies at (m dx + ox, n dy + oy)
+ * of the unshifted geometry. A width <= 0 leaves that axis unlimited. */
+typedef struct {
+    double ox, oy; /* destination-window offset [m] */
+    double cx, wx; /* band-limit centre and full width along x [1/m] */
+    double cy, wy; /* band-limit centre and full width along y [1/m] */
+} cwo_shift;
+
+/* Shifted angular spectrum propagation; same layout and scratch as cwo_asm. Complex64
+ * storage only (other precisions: CWO_ERR_UNSUPPORTED). A null or non-finite shift is
+ * CWO_ERR_INVALID. */
+cwo_status cwo_asm_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_shift* shift,
+                           const void* in, void* out, void* hip_stream);
+
+/* Band limit of the on-axis case (ox = oy = 0, centred band): sets shift to zero offsets
+ * and centres and wx = 2 / (lambda sqrt((2 dfx z)^2 + 1)), dfx = 1/(Mx dx) (M the padded
+ * size), wy likewise: the band-limited angular spectrum condition of the reference the
+ * section cites, where the transfer function's phase advances by pi per frequency step.
+ * Host only; validates p like cwo_asm. */
+cwo_status cwo_band_limit(const cwo_params* p, cwo_shift* shift);
+
 /* z-stack: one field propagated to nz distances, the paper's 3-D field built by stacking
  * 2-D propagations (Sec. 2.3, Diffract3D). p->kind selects CWO_ANGULAR or
  * CWO_FRESNEL_CONV (0 is CWO_ERR_INVALID here); p->z is ignored; z is a HOST array of nz

@@ -348,7 +348,8 @@ cwo_status begin(cwo_ctx* c) {
 }
 
 cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kind,
-                            const void* in, void* out, hipStream_t s) {
+                            const void* in, void* out, hipStream_t s,
+                            const cwo::AsmShift* shift = nullptr) {
     cwo_status st = CWO_OK;
     const Geometry g = geometry(p);
     const float2* twx = twiddle_table(c, g.mx, s, &st);
@@ -386,7 +387,13 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
                 return cwo::launch_row_fwd(fin, buf, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s);
             }));
-    if (kind == CWO_ANGULAR) {
+    if (kind == CWO_ANGULAR && shift) {
+        const cwo::AsmScalars a = asm_scalars(p, g, p->z);
+        CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                    return cwo::launch_col_asm_shifted((float2*)buf, g.ny, g.my, g.mx, a, *shift,
+                                                       twy, s);
+                }));
+    } else if (kind == CWO_ANGULAR) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, sto, twy, s);
@@ -404,7 +411,7 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
 }
 
 cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
-                     void* stream) {
+                     void* stream, const cwo::AsmShift* shift = nullptr) {
     if (!c) return CWO_ERR_INVALID;
     cwo_status st = validate(p, kind, true);
     if (st != CWO_OK) return st;
@@ -412,7 +419,7 @@ cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, 
     std::lock_guard<std::mutex> lock(c->mu);
     st = begin(c);
     if (st != CWO_OK) return st;
-    return propagate_locked(c, c->ws, p, kind, in, out, (hipStream_t)stream);
+    return propagate_locked(c, c->ws, p, kind, in, out, (hipStream_t)stream, shift);
 }
 
 // One field to nz distances; plane k goes to outs[k]. The row transform of the field
@@ -756,6 +763,32 @@ cwo_status cwo_asm(cwo_ctx* c, const cwo_params* p, const void* in, void* out, v
 
 cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* out, void* stream) {
     return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream);
+}
+
+cwo_status cwo_asm_shifted(cwo_ctx* c, const cwo_params* p, const cwo_shift* sh, const void* in,
+                           void* out, void* stream) {
+    if (!c || !p || !sh) return CWO_ERR_INVALID;
+    for (double v : {sh->ox, sh->oy, sh->cx, sh->wx, sh->cy, sh->wy})
+        if (!std::isfinite(v)) return CWO_ERR_INVALID;
+    cwo_status st = validate(p, CWO_ANGULAR, true);
+    if (st != CWO_OK) return st;
+    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    const cwo::AsmShift shift{sh->ox, sh->oy, sh->cx, sh->wx, sh->cy, sh->wy};
+    return propagate(c, p, CWO_ANGULAR, in, out, stream, &shift);
+}
+
+cwo_status cwo_band_limit(const cwo_params* p, cwo_shift* sh) {
+    if (!p || !sh) return CWO_ERR_INVALID;
+    const cwo_status st = validate(p, CWO_ANGULAR, true);
+    if (st != CWO_OK) return st;
+    const Geometry g = geometry(p);
+    auto width = [&](int m, double d) {
+        const double df = 1.0 / ((double)m * d);
+        const double t = 2.0 * df * p->z;
+        return 2.0 / (p->wavelength * std::sqrt(t * t + 1.0));
+    };
+    *sh = cwo_shift{0.0, 0.0, 0.0, width(g.mx, p->dx), 0.0, width(g.my, p->dy)};
+    return CWO_OK;
 }
 
 cwo_status cwo_zstack(cwo_ctx* c, const cwo_params* p, const double* z, int32_t nz, const void* in,

@@ -13,6 +13,15 @@ struct AsmScalars {
     double zl;        // z / wavelength
 };
 
+// Shifted angular spectrum method (Sec. 2.1.5): destination-window offset and the two
+// band-limit Rect functions, in the units of the caller's cwo_shift; a width <= 0
+// leaves that axis unlimited.
+struct AsmShift {
+    double ox, oy;  // [m]
+    double cx, wx;  // [1/m]
+    double cy, wy;  // [1/m]
+};
+
 // The angular-spectrum column pass takes the fast phase form when every bin of the
 // grid has (lambda fx)^2 + (lambda fy)^2 <= this bound, the exact FP64 form otherwise.
 constexpr double kAsmFastMaxS = 0.05;
@@ -53,6 +62,9 @@ hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, i
                           hipStream_t s);
 hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t plane,
                           const AsmScalars& a, const Storage& st, const float2* tw, hipStream_t s);
+// Column pass of the shifted angular spectrum method (complex64 storage only).
+hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const AsmScalars& a,
+                                  const AsmShift& sh, const float2* tw, hipStream_t s);
 hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
                               const float2* hx, const float2* hy, const Storage& st,
                               const float2* tw, hipStream_t s);

@@ -23,7 +23,7 @@
 //             h_F factorises into two 1-D transforms of chirps, computed here
 //             by FP64 FFTs.
 
-#include "kernel_common.hpp"
+#include "column.hpp"
 
 namespace cwo {
 
@@ -127,176 +127,6 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(const float2*
         }
 #pragma unroll
         for (int r = 0; r < NL; ++r) cur[r] = nxt[r];
-    }
-}
-
-// ---- column pass: FFT, transfer function, IFFT, crop --------------------------
-
-// Exact form, for any parameters: per bin in FP64, the propagating test s <= 1
-// evaluated with the same operations as the FP64 reference, sine/cosine of the
-// reduced phase in FP32.
-struct AsmH {
-    double dfx, dfy;  // frequency pitches 1/(Mx dx), 1/(My dy)
-    double lam;       // wavelength
-    double zl;        // z / lambda: phase in revolutions per unit sqrt(1 - s)
-    int mx, my;
-    struct Col {
-        double ax2;
-    };
-    __device__ __forceinline__ Col column(int p) const {
-        const double pp = (double)(p < mx / 2 ? p : p - mx);
-        const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
-        return Col{__dmul_rn(ax, ax)};
-    }
-    struct Row {
-        double ay2;
-    };
-    __device__ __forceinline__ Row row(int q) const {
-        const double qq = (double)(q < my / 2 ? q : q - my);
-        const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
-        return Row{__dmul_rn(ay, ay)};
-    }
-    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
-        // s = (lambda*fx)^2 + (lambda*fy)^2 with fx = p'*dfx, evaluated without contraction
-        const double s = __dadd_rn(rw.ay2, c.ax2);
-        if (!(s <= 1.0)) return make_float2(0.f, 0.f);  // evanescent bin
-        const double t = zl * __dsqrt_rn(1.0 - s);       // revolutions
-        const float r = (float)(t - rint(t));            // [-0.5, 0.5]
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    }
-};
-
-// Fast form, used when every bin has s <= 0.05 (so none is evanescent). With
-// T(s) = 1 - s/2 - sqrt(1 - s), the phase in revolutions splits exactly into
-//     (z/lambda) sqrt(1 - s) = zl - zl*a/2 - zl*b/2 - zl*T(s),  s = a + b,
-// a = (lambda fx)^2 per column, b = (lambda fy)^2 per row. Every large term is
-// reduced modulo one revolution in FP64 before it is rounded to FP32; T(s) is the
-// power series sum_{n>=2} c_n s^n (c_n = (2n-3)!!/(2^n n!)) to n = 9, whose
-// truncation error is below 3e-12 relative for s <= 0.05. The hardware sine and
-// cosine take the reduced phase in revolutions.
-struct AsmHFast {
-    double lam_dfx, lam_dfy;  // lambda/(Mx dx), lambda/(My dy)
-    double zl, half_zl;       // z/lambda, z/(2 lambda)
-    float c0;                 // zl reduced to [-0.5, 0.5]
-    int mx, my;
-    struct Col {
-        double a;
-        float ca;  // c0 - reduced(zl*a/2)
-    };
-    __device__ __forceinline__ Col column(int p) const {
-        const double x = (double)(p < mx / 2 ? p : p - mx) * lam_dfx;
-        const double a = x * x;
-        const double ta = half_zl * a;
-        return Col{a, c0 - (float)(ta - rint(ta))};
-    }
-    struct Row {
-        double b, hb;  // (lambda fy)^2 and zl*b/2
-    };
-    __device__ __forceinline__ Row row(int q) const {
-        const double y = (double)(q < my / 2 ? q : q - my) * lam_dfy;
-        const double b = y * y;
-        return Row{b, half_zl * b};
-    }
-    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
-        const double s = c.a + rw.b;
-        double poly = 715.0 / 65536.0;
-        poly = fma(poly, s, 429.0 / 32768.0);
-        poly = fma(poly, s, 33.0 / 2048.0);
-        poly = fma(poly, s, 21.0 / 1024.0);
-        poly = fma(poly, s, 7.0 / 256.0);
-        poly = fma(poly, s, 5.0 / 128.0);
-        poly = fma(poly, s, 1.0 / 16.0);
-        poly = fma(poly, s, 1.0 / 8.0);
-        // zl*b/2 + zl*T(s), reduced, in FP64
-        const double u = fma(zl * (s * s), poly, rw.hb);
-        float r = c.ca - (float)(u - rint(u));
-        r -= rintf(r);
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    }
-};
-
-struct FresnelH {
-    const float2* __restrict__ hx;  // Mx entries, carries the constant C
-    const float2* __restrict__ hy;  // My entries
-    struct Col {
-        float2 h;
-    };
-    struct Row {
-        float2 h;
-    };
-    __device__ __forceinline__ Col column(int p) const { return Col{hx[p]}; }
-    __device__ __forceinline__ Row row(int q) const { return Row{hy[q]}; }
-    __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
-        return cmul(c.h, rw.h);
-    }
-};
-
-// Column pass: forward FFT of COLS columns, multiplication by the transfer function,
-// inverse FFT, in place; one (plane, column tile) item per block.
-template <int M, bool HALF, class HF, class ST>
-__global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_col(typename ST::E* __restrict__ buf,
-                                                              int ny, int mx, int batch,
-                                                              size_t plane, HF hf, float hscale,
-                                                              const float2* __restrict__ tw) {
-    using C = ColCfg<M>;
-    constexpr int E = C::E, T = C::T, P = C::P;
-    using SE = typename ST::E;
-    using PK = Pack<SE, P>;
-    __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
-    float2* lds = reinterpret_cast<float2*>(lds4);
-    const int tid = threadIdx.x;
-    const int pair = tid / T, j = tid % T;
-    float2* my_lds = lds + pair * C::LDS_PAIR;
-    TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
-    const int ntiles = (mx + C::COLS - 1) / C::COLS;
-    const int it = xcd_remap(blockIdx.x, gridDim.x);
-    const int pl = it / ntiles, tile = it - pl * ntiles;
-    const int col0 = (tile * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
-    const bool active = col0 < mx;                  // tiles may overhang narrow planes
-    const int col = active ? col0 : 0;
-    SE* base = buf + pl * plane + col;
-    float2 v[P][E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int y = j + r * T;
-        const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
-        if (ld) {
-            const PK t = *reinterpret_cast<const PK*>(base + (size_t)y * mx);
-#pragma unroll
-            for (int p = 0; p < P; ++p) v[p][r] = ST::dec(t.e[p]);
-        } else {
-#pragma unroll
-            for (int p = 0; p < P; ++p) v[p][r] = make_float2(0.f, 0.f);
-        }
-    }
-    typename HF::Col hc[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
-    if constexpr (E == 16) fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
-    else fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, tw);
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const typename HF::Row hr = hf.row(j + r * T);
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            float2 h = hf(hc[p], hr);
-            if (hscale != 1.0f) h = make_float2(h.x * hscale, h.y * hscale);
-            v[p][r] = cmul(v[p][r], h);
-        }
-    }
-    if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
-    else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int y = j + r * T;
-        const bool st = active && (HALF ? (r < E / 2) : (y < ny));
-        if (st) {
-            PK t;
-#pragma unroll
-            for (int p = 0; p < P; ++p) t.e[p] = ST::enc(v[p][r]);
-            *reinterpret_cast<PK*>(base + (size_t)y * mx) = t;
-        }
     }
 }
 

@@ -81,6 +81,13 @@ _lib = None
 _lib_lock = threading.Lock()
 
 # name -> (restype, argtypes) for every symbol include/cwo.h declares
+class Shift(ctypes.Structure):
+    """cwo_shift: destination-window offset [m] and band-limit centres/widths [1/m]."""
+    _fields_ = [("ox", ctypes.c_double), ("oy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("wx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("wy", ctypes.c_double)]
+
+
 SIGNATURES = {
     "cwo_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t]),
     "cwo_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -88,6 +95,10 @@ SIGNATURES = {
                                  ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_asm_shifted": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                         ctypes.POINTER(Shift), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "cwo_band_limit": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.POINTER(Shift)]),
     "cwo_zstack": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -235,6 +246,20 @@ class Context:
         return self._propagate(self._lib.cwo_fresnel, FRESNEL_CONV, u, dx, dy, wavelength, z,
                                precision, nopad, out, stream)
 
+    def asm_shifted(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, ox=0.0, oy=0.0,
+                    cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None):
+        """Shifted angular spectrum propagation: window offset (ox, oy) [m], band limits
+        Rect((fx - cx)/wx) Rect((fy - cy)/wy) [1/m] (a width <= 0: no limit)."""
+        sh = Shift(float(ox), float(oy), float(cx), float(wx), float(cy), float(wy))
+        lib = self._lib
+
+        def call(h, pp, a, b, s):
+            return lib.cwo_asm_shifted(h, pp, ctypes.byref(sh), a, b, s)
+
+        call.__name__ = "cwo_asm_shifted"
+        return self._propagate(call, ANGULAR, u, dx, dy, wavelength, z, "f32", nopad, out,
+                               stream)
+
 
     def zstack(self, u, z, dx=10e-6, dy=None, wavelength=633e-9, kind="asm", precision="f32",
                nopad=False, out=None, stream=None):
@@ -348,6 +373,16 @@ class Context:
 
 
 _default = {}
+
+
+def band_limit(nx, ny, dx, dy=None, wavelength=633e-9, z=0.1, nopad=False):
+    """(wx, wy): full widths [1/m] of the on-axis band limit (cwo_band_limit)."""
+    p = make_params(nx, ny, dx, dy, wavelength, z, ANGULAR, "f32", nopad)
+    sh = Shift()
+    st = load().cwo_band_limit(ctypes.byref(p), ctypes.byref(sh))
+    if st != CWO_OK:
+        raise CwoError(st, "cwo_band_limit")
+    return sh.wx, sh.wy
 
 
 def context(device: int = 0) -> Context:

@@ -110,3 +110,21 @@ def test_low_precision_storage_params():
         assert cwo.load().cwo_scratch_bytes(ctypes.byref(p)) == 4 * 256 * 512
         p = cwo.make_params(256, 256, 10e-6, z=0.1, precision=prec, nopad=True)
         assert cwo.check_params(p, cwo.ANGULAR) == cwo.CWO_ERR_UNSUPPORTED
+
+
+def test_band_limit_host_function():
+    from oracle import shifted_asm as S
+    lib = cwo.load()
+    for n, d, lam, z, nopad in [(2048, 8e-6, 532e-9, 0.5, False), (256, 10e-6, 633e-9, 2.0, True),
+                                (64, 4e-6, 473e-9, -0.05, False)]:
+        wx, wy = cwo.band_limit(n, n // 2, d, 2 * d, lam, z, nopad)
+        assert math.isclose(wx, S.band_limit(n, d, lam, z, nopad), rel_tol=1e-14)
+        assert math.isclose(wy, S.band_limit(n // 2, 2 * d, lam, z, nopad), rel_tol=1e-14)
+    sh = cwo.Shift()
+    p = cwo.make_params(64, 64, 10e-6, z=0.1)
+    assert lib.cwo_band_limit(None, ctypes.byref(sh)) == cwo.CWO_ERR_INVALID
+    assert lib.cwo_band_limit(ctypes.byref(p), None) == cwo.CWO_ERR_INVALID
+    p.dx = 0.0
+    assert lib.cwo_band_limit(ctypes.byref(p), ctypes.byref(sh)) == cwo.CWO_ERR_INVALID
+    assert lib.cwo_asm_shifted(None, ctypes.byref(p), ctypes.byref(sh), None, None,
+                               None) == cwo.CWO_ERR_INVALID

@@ -1,0 +1,145 @@
+"""GPU parity of the shifted angular spectrum method (cwo_asm_shifted) with the FP64 oracle
+(relative L2 <= 1e-5 per plane, element-wise <= 1e-5 of the plane's peak)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D, shifted_asm as S
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1107_5578_amd import cwo
+    c = cwo.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def check(y, ref, label, rel_tol=1e-5, elem_tol=1e-5):
+    rl = D.rel_l2(y, ref)
+    peak = float(np.max(np.abs(ref)))
+    emax = float(np.max(np.abs(y.astype(np.complex128) - ref)))
+    note("%s rel_l2=%.3e max_abs_err/peak=%.3e" % (label, rl, emax / peak))
+    assert rl <= rel_tol, (label, rl)
+    assert emax <= elem_tol * peak, (label, emax / peak)
+
+
+CASES = [
+    # n, ny, dx, dy, lam, z, ox, oy, band ("bl" = on-axis limit, None, or (cx, wx, cy, wy) in df units)
+    (256, 256, 10e-6, 10e-6, 633e-9, 0.1, 3.7e-4, -1.25e-4, "bl"),
+    (128, 64, 6e-6, 9e-6, 532e-9, 0.02, 0.0, 2.1e-4, (10.5, 60.0, -4.0, 40.0)),
+    (64, 64, 8e-6, 8e-6, 473e-9, -0.05, -9.9e-5, 0.0, None),
+    (16, 32, 8e-6, 8e-6, 633e-9, 0.3, 1.6e-5, 8e-6, (0.0, 9.0, 3.0, 17.0)),
+]
+
+
+@pytest.mark.parametrize("n,ny,dx,dy,lam,z,ox,oy,band", CASES)
+def test_shifted_parity(ctx, n, ny, dx, dy, lam, z, ox, oy, band):
+    import torch
+    u = W.uniform_random_field(n, 500 + n + ny, ny=ny)
+    if band == "bl":
+        wx = S.band_limit(n, dx, lam, z)
+        wy = S.band_limit(ny, dy, lam, z)
+        cx = cy = 0.0
+    elif band is None:
+        cx = wx = cy = wy = 0.0
+    else:
+        dfx, dfy = 1.0 / (2 * n * dx), 1.0 / (2 * ny * dy)
+        cx, wx, cy, wy = band[0] * dfx, band[1] * dfx, band[2] * dfy, band[3] * dfy
+    note("shifted %dx%d z=%g o=(%g,%g) band=%s" % (n, ny, z, ox, oy, band))
+    t = torch.from_numpy(u).cuda()
+    y = ctx.asm_shifted(t, dx, dy, lam, z, ox, oy, cx, wx, cy, wy)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, dx, dy, lam, z, ox, oy, cx, wx, cy, wy)
+    check(y.cpu().numpy(), ref, "shifted %dx%d" % (n, ny))
+
+
+def test_shifted_2048_band_limited(ctx):
+    # the plane workload's geometry, far beyond the critical distance, shifted off axis
+    import torch
+    cfg = W.PLANE_2048
+    u = W.field_for(cfg)
+    z = 3.0
+    wx = S.band_limit(2048, cfg.pitch, cfg.wavelength, z)
+    note("shifted 2048 z=%g band=%g" % (z, wx))
+    t = torch.from_numpy(u).cuda()
+    y = ctx.asm_shifted(t, cfg.pitch, cfg.pitch, cfg.wavelength, z, 1.2e-3, -0.4e-3, 0.0, wx,
+                        0.0, wx)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, cfg.pitch, cfg.pitch, cfg.wavelength, z, 1.2e-3, -0.4e-3, 0.0, wx, 0.0,
+                      wx)
+    check(y.cpu().numpy(), ref, "shifted 2048")
+
+
+def test_exact_phase_path_with_shift(ctx):
+    # 0.6 um pitch: s > 0.05 selects the FP64 per-bin form, evanescent corners included
+    import torch
+    u = W.uniform_random_field(128, 91)
+    t = torch.from_numpy(u).cuda()
+    df = 1.0 / (256 * 0.6e-6)
+    y = ctx.asm_shifted(t, 0.6e-6, 0.6e-6, 633e-9, 2e-5, 1.1e-5, 3.0e-6, 5 * df, 150 * df, 0.0, 0.0)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, 0.6e-6, 0.6e-6, 633e-9, 2e-5, 1.1e-5, 3.0e-6, 5 * df, 150 * df, 0.0, 0.0)
+    check(y.cpu().numpy(), ref, "shifted exact-phase")
+
+
+def test_masked_plane_waves_are_suppressed(ctx):
+    # a no-pad plane wave whose bin lies outside the band: only the complex64 rounding of
+    # the input (spread over all bins, ~1e-8 of the amplitude) can pass
+    import torch
+    n, d = 32, 8e-6
+    j = np.arange(n)
+    u = (np.exp(2j * math.pi * (4 * j[:, None] - 9 * j[None, :]) / n)).astype(np.complex64)
+    df = 1.0 / (n * d)
+    t = torch.from_numpy(u).cuda()
+    y = ctx.asm_shifted(t, d, d, 532e-9, 0.03, 1e-5, 0.0, 2 * df, 16 * df, 0.0, 0.0, nopad=True)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, d, d, 532e-9, 0.03, 1e-5, 0.0, 2 * df, 16 * df, 0.0, 0.0, nopad=True)
+    yn = y.cpu().numpy()
+    note("masked plane wave: max |y| = %.3e, oracle %.3e" % (np.max(np.abs(yn)), np.max(np.abs(ref))))
+    assert np.max(np.abs(yn)) < 1e-6
+    assert np.max(np.abs(yn - ref)) < 1e-6
+    y = ctx.asm_shifted(t, d, d, 532e-9, 0.03, 1e-5, 0.0, -9 * df, 2 * df, 0.0, 0.0, nopad=True)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, d, d, 532e-9, 0.03, 1e-5, 0.0, -9 * df, 2 * df, 0.0, 0.0, nopad=True)
+    check(y.cpu().numpy(), ref, "band edge plane wave")
+
+
+def test_zero_shift_matches_plain_call(ctx):
+    import torch
+    u = W.uniform_random_field(256, 7)
+    t = torch.from_numpy(u).cuda()
+    a = ctx.asm(t, 8e-6, 8e-6, 532e-9, 0.2)
+    b = ctx.asm_shifted(t, 8e-6, 8e-6, 532e-9, 0.2)
+    torch.cuda.synchronize()
+    assert D.rel_l2(b.cpu().numpy(), a.cpu().numpy().astype(np.complex128)) <= 1e-7
+
+
+def test_shifted_errors(ctx):
+    import torch
+    from paper_1107_5578_amd import cwo
+    t = torch.from_numpy(W.uniform_random_field(64, 3)).cuda()
+    with pytest.raises(cwo.CwoError) as e:
+        ctx.asm_shifted(t, 8e-6, 8e-6, 532e-9, 0.2, ox=math.nan)
+    assert e.value.status == cwo.CWO_ERR_INVALID
+    p = cwo.make_params(64, 64, 8e-6, z=0.2, precision="f16")
+    sh = cwo.Shift()
+    out = torch.empty_like(t)
+    import ctypes
+    st = ctx._lib.cwo_asm_shifted(ctx.handle, ctypes.byref(p), ctypes.byref(sh),
+                                  ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  None)
+    assert st == cwo.CWO_ERR_UNSUPPORTED
