@@ -54,7 +54,7 @@ typedef enum {
 } cwo_status;
 
 /* Diffraction kinds (the paper's CWO_ANGULAR and CWO_FRESNEL_CONV selectors). */
-typedef enum { CWO_ANGULAR = 1, CWO_FRESNEL_CONV = 2 } cwo_kind;
+typedef enum { CWO_ANGULAR = 1, CWO_FRESNEL_CONV = 2, CWO_FRESNEL_FOURIER = 3 } cwo_kind;
 
 /* Storage precision of the padded intermediate planes; butterflies and the transfer
  * function are always FP32 (phase reduction FP64) and the field in/out is always
@@ -107,6 +107,20 @@ cwo_status cwo_asm(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
  * cwo_asm. The two 1-D factors of FFT[h_F] are cached per parameter set. */
 cwo_status cwo_fresnel(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
                        void* hip_stream);
+
+/* Fresnel diffraction, Fourier form (Sec. 2.1.2, Eqs. fre_fourier1 - fre_fourier3): one
+ * unpadded 2-D FFT of the field times exp(i pi (x1^2 + y1^2)/(lambda z)), then times
+ * exp(i pi (x2^2 + y2^2)/(lambda z)) and dx dy exp(i k z)/(i lambda z). Sample positions are
+ * centred (array index j is coordinate (j - N/2) * pitch) on both planes; the destination
+ * pitch is lambda z/(N dx) along x and lambda z/(N dy) along y (negative for z < 0: mirrored
+ * axes). in, out: device complex64 [ny][nx]; in == out is allowed. p->kind is 0 or
+ * CWO_FRESNEL_FOURIER; z == 0 or any flag is CWO_ERR_INVALID; complex64 storage only
+ * (CWO_ERR_UNSUPPORTED otherwise). Scratch: 2 (nx + ny) complex64 of chirp tables. */
+cwo_status cwo_fresnel_fourier(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
+                               void* hip_stream);
+
+/* Destination pitch of cwo_fresnel_fourier for p (host only; validates p the same way). */
+cwo_status cwo_fresnel_fourier_pitch(const cwo_params* p, double* dx2, double* dy2);
 
 /* Shifted angular spectrum method (Sec. 2.1.5, Eqs. shift_ang1 and shift_ang2): the
  * transfer function of cwo_asm times exp(i 2 pi (ox fx + oy fy)) and times the band-limit

@@ -55,13 +55,15 @@ struct Workspace {
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     Buffer gsnum;                     // per-row error partials of the ping-pong iteration
     Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
+    Buffer fourier;                   // chirp tables of the Fresnel Fourier form
     std::list<FresnelEntry> fresnel;  // most recently used first
     size_t budget = 0;                // 0: unbounded (serving slots are bounded by admission)
     size_t held() const {
-        return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes;
+        return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes +
+               fourier.bytes;
     }
     void release() {
-        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork}) {
+        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->bytes = 0;
@@ -765,6 +767,63 @@ cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* ou
     return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream);
 }
 
+// Fresnel Fourier form: sizes as the other kinds, z != 0, no flags, complex64 only.
+cwo_status validate_fourier(const cwo_params* p) {
+    if (!p) return CWO_ERR_INVALID;
+    if (p->kind != 0 && p->kind != CWO_FRESNEL_FOURIER) return CWO_ERR_INVALID;
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
+    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
+    if (p->flags != 0) return CWO_ERR_INVALID;
+    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
+    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
+        p->ny > kMaxN)
+        return CWO_ERR_UNSUPPORTED;
+    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    return CWO_OK;
+}
+
+cwo_status cwo_fresnel_fourier(cwo_ctx* c, const cwo_params* p, const void* in, void* out,
+                               void* stream) {
+    if (!c) return CWO_ERR_INVALID;
+    cwo_status st = validate_fourier(p);
+    if (st != CWO_OK) return st;
+    if (!in || !out) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = begin(c);
+    if (st != CWO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const float2* twx = twiddle_table(c, p->nx, s, &st);
+    if (!twx) return st;
+    const float2* twy = twiddle_table(c, p->ny, s, &st);
+    if (!twy) return st;
+    float2* tabs = (float2*)ensure(c, c->ws, c->ws.fourier,
+                                   sizeof(float2) * 2 * (size_t)(p->nx + p->ny), &st);
+    if (!tabs) return st;
+    cwo::FourierPlan fp;
+    fp.nx = p->nx;
+    fp.ny = p->ny;
+    fp.dx = p->dx;
+    fp.dy = p->dy;
+    fp.dx2 = p->wavelength * p->z / ((double)p->nx * p->dx);
+    fp.dy2 = p->wavelength * p->z / ((double)p->ny * p->dy);
+    fp.inv2lz = 0.5 / (p->wavelength * p->z);
+    fresnel_constant(p->dx, p->dy, p->wavelength, p->z, &fp.cre, &fp.cim);
+    CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
+                return cwo::launch_fresnel_fourier((const float2*)in, (float2*)out, tabs, fp, twx,
+                                                   twy, s);
+            }));
+    return CWO_OK;
+}
+
+cwo_status cwo_fresnel_fourier_pitch(const cwo_params* p, double* dx2, double* dy2) {
+    const cwo_status st = validate_fourier(p);
+    if (st != CWO_OK) return st;
+    if (!dx2 || !dy2) return CWO_ERR_INVALID;
+    *dx2 = p->wavelength * p->z / ((double)p->nx * p->dx);
+    *dy2 = p->wavelength * p->z / ((double)p->ny * p->dy);
+    return CWO_OK;
+}
+
 cwo_status cwo_asm_shifted(cwo_ctx* c, const cwo_params* p, const cwo_shift* sh, const void* in,
                            void* out, void* stream) {
     if (!c || !p || !sh) return CWO_ERR_INVALID;
@@ -890,7 +949,10 @@ cwo_status cwo_profile_read(cwo_ctx* c, int32_t stage, double* total_ms, int64_t
     return CWO_OK;
 }
 
-cwo_status cwo_check_params(const cwo_params* p, int32_t kind) { return validate(p, kind, true); }
+cwo_status cwo_check_params(const cwo_params* p, int32_t kind) {
+    if (kind == CWO_FRESNEL_FOURIER) return validate_fourier(p);
+    return validate(p, kind, true);
+}
 
 size_t cwo_scratch_bytes(const cwo_params* p) {
     if (!p) return 0;

@@ -126,4 +126,18 @@ struct FresnelPlanes {
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s);
 
+// Fresnel diffraction in Fourier form (Sec. 2.1.2): parameters of the chirp tables.
+struct FourierPlan {
+    int nx, ny;
+    double dx, dy;    // source pitch [m]
+    double dx2, dy2;  // destination pitch lambda z/(N d) [m]
+    double inv2lz;    // 1/(2 lambda z)
+    double cre, cim;  // dx dy exp(i k z)/(i lambda z)
+};
+// in, out: complex64 [ny][nx] (may alias); tabs: 2 (nx + ny) complex64 of scratch;
+// twx, twy: twiddle tables of length nx and ny.
+hipError_t launch_fresnel_fourier(const float2* in, float2* out, float2* tabs,
+                                  const FourierPlan& fp, const float2* twx, const float2* twy,
+                                  hipStream_t s);
+
 }  // namespace cwo

@@ -27,6 +27,7 @@ CWO_ERR_NOTFOUND = -5
 
 ANGULAR = 1
 FRESNEL_CONV = 2
+FRESNEL_FOURIER = 3
 
 PREC_F32 = 0
 PREC_F16 = 1
@@ -99,6 +100,11 @@ SIGNATURES = {
                                          ctypes.POINTER(Shift), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
     "cwo_band_limit": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.POINTER(Shift)]),
+    "cwo_fresnel_fourier": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_fresnel_fourier_pitch": (ctypes.c_int32, [ctypes.POINTER(Params),
+                                                   ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_double)]),
     "cwo_zstack": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -246,6 +252,13 @@ class Context:
         return self._propagate(self._lib.cwo_fresnel, FRESNEL_CONV, u, dx, dy, wavelength, z,
                                precision, nopad, out, stream)
 
+    def fresnel_fourier(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, out=None,
+                        stream=None):
+        """Fresnel diffraction, Fourier form (one unpadded FFT); the destination pitch is
+        fresnel_fourier_pitch(...)."""
+        return self._propagate(self._lib.cwo_fresnel_fourier, FRESNEL_FOURIER, u, dx, dy,
+                               wavelength, z, "f32", False, out, stream)
+
     def asm_shifted(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, ox=0.0, oy=0.0,
                     cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None):
         """Shifted angular spectrum propagation: window offset (ox, oy) [m], band limits
@@ -373,6 +386,16 @@ class Context:
 
 
 _default = {}
+
+
+def fresnel_fourier_pitch(nx, ny, dx, dy=None, wavelength=633e-9, z=0.1):
+    """(dx2, dy2): destination pitch of the Fresnel Fourier form [m]."""
+    p = make_params(nx, ny, dx, dy, wavelength, z, FRESNEL_FOURIER, "f32", False)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    st = load().cwo_fresnel_fourier_pitch(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b))
+    if st != CWO_OK:
+        raise CwoError(st, "cwo_fresnel_fourier_pitch")
+    return a.value, b.value
 
 
 def band_limit(nx, ny, dx, dy=None, wavelength=633e-9, z=0.1, nopad=False):

@@ -128,3 +128,27 @@ def test_band_limit_host_function():
     assert lib.cwo_band_limit(ctypes.byref(p), ctypes.byref(sh)) == cwo.CWO_ERR_INVALID
     assert lib.cwo_asm_shifted(None, ctypes.byref(p), ctypes.byref(sh), None, None,
                                None) == cwo.CWO_ERR_INVALID
+
+
+def test_fresnel_fourier_params_and_pitch():
+    from oracle import fresnel_fourier as F
+    lib = cwo.load()
+    K = cwo.FRESNEL_FOURIER
+    p = cwo.make_params(512, 256, 10e-6, 8e-6, 633e-9, 0.2, kind=K)
+    assert cwo.check_params(p, K) == cwo.CWO_OK
+    dx2, dy2 = cwo.fresnel_fourier_pitch(512, 256, 10e-6, 8e-6, 633e-9, 0.2)
+    assert math.isclose(dx2, F.destination_pitch(512, 10e-6, 633e-9, 0.2), rel_tol=1e-15)
+    assert math.isclose(dy2, F.destination_pitch(256, 8e-6, 633e-9, 0.2), rel_tol=1e-15)
+    dx2, _ = cwo.fresnel_fourier_pitch(64, 64, 10e-6, 10e-6, 633e-9, -0.1)
+    assert dx2 < 0
+    bad = [dict(z=0.0), dict(z=math.nan), dict(dx=0.0), dict(flags=1), dict(kind=1)]
+    for b in bad:
+        q = cwo.make_params(64, 64, 10e-6, z=0.1, kind=K)
+        for k, v in b.items():
+            setattr(q, k, v)
+        assert cwo.check_params(q, K) == cwo.CWO_ERR_INVALID, b
+    q = cwo.make_params(64, 64, 10e-6, z=0.1, kind=K, precision="f16")
+    assert cwo.check_params(q, K) == cwo.CWO_ERR_UNSUPPORTED
+    q = cwo.make_params(8192, 64, 10e-6, z=0.1, kind=K)
+    assert cwo.check_params(q, K) == cwo.CWO_ERR_UNSUPPORTED
+    assert lib.cwo_fresnel_fourier(None, ctypes.byref(p), None, None, None) == cwo.CWO_ERR_INVALID
