@@ -54,7 +54,12 @@ typedef enum {
 } cwo_status;
 
 /* Diffraction kinds (the paper's CWO_ANGULAR and CWO_FRESNEL_CONV selectors). */
-typedef enum { CWO_ANGULAR = 1, CWO_FRESNEL_CONV = 2, CWO_FRESNEL_FOURIER = 3 } cwo_kind;
+typedef enum {
+    CWO_ANGULAR = 1,
+    CWO_FRESNEL_CONV = 2,
+    CWO_FRESNEL_FOURIER = 3,
+    CWO_FRESNEL_SHIFTED = 4
+} cwo_kind;
 
 /* Storage precision of the padded intermediate planes; butterflies and the transfer
  * function are always FP32 (phase reduction FP64) and the field in/out is always
@@ -121,6 +126,26 @@ cwo_status cwo_fresnel_fourier(cwo_ctx* ctx, const cwo_params* p, const void* in
 
 /* Destination pitch of cwo_fresnel_fourier for p (host only; validates p the same way). */
 cwo_status cwo_fresnel_fourier_pitch(const cwo_params* p, double* dx2, double* dy2);
+
+/* Shifted Fresnel diffraction (Sec. 2.1.3, Eqs. shift_fre1 - shift_fre3): the Fresnel sum
+ *   u1[m1, n1] = dx0 dy0 exp(i k z)/(i lambda z)
+ *                * sum u0[m0, n0] exp(i pi ((x1 - x0)^2 + (y1 - y0)^2)/(lambda z))
+ * from a source window (pitch p->dx, p->dy, centre ox0, oy0) to a destination window of
+ * the same size (pitch dx1, dy1, centre ox1, oy1), x0 = m0 dx + ox0, x1 = m1 dx1 + ox1 with
+ * centred indices m = j - N/2, computed as a chirp convolution on the 2N x 2N padded grid
+ * (3 FFTs, like cwo_fresnel). */
+typedef struct {
+    double dx1, dy1;  /* destination pitch [m], finite and > 0 */
+    double ox0, oy0;  /* source window centre [m] */
+    double ox1, oy1;  /* destination window centre [m] */
+} cwo_sfresnel;
+
+/* Shifted Fresnel propagation. in, out: device complex64 [ny][nx] (in == out allowed);
+ * p->kind is 0 or CWO_FRESNEL_SHIFTED; z == 0, any flag, a null window or a non-finite or
+ * non-positive window value is CWO_ERR_INVALID; complex64 storage only. Scratch: ny * 2nx
+ * complex64 plus the chirp and kernel-factor tables. */
+cwo_status cwo_fresnel_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_sfresnel* window,
+                               const void* in, void* out, void* hip_stream);
 
 /* Shifted angular spectrum method (Sec. 2.1.5, Eqs. shift_ang1 and shift_ang2): the
  * transfer function of cwo_asm times exp(i 2 pi (ox fx + oy fy)) and times the band-limit

@@ -824,6 +824,93 @@ cwo_status cwo_fresnel_fourier_pitch(const cwo_params* p, double* dx2, double* d
     return CWO_OK;
 }
 
+// Shifted Fresnel: sizes as the other kinds (padded 2N), z != 0, no flags, complex64 only.
+cwo_status validate_sfresnel(const cwo_params* p, const cwo_sfresnel* w) {
+    if (!p || !w) return CWO_ERR_INVALID;
+    if (p->kind != 0 && p->kind != CWO_FRESNEL_SHIFTED) return CWO_ERR_INVALID;
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
+    if (!finite_pos(w->dx1) || !finite_pos(w->dy1)) return CWO_ERR_INVALID;
+    for (double v : {w->ox0, w->oy0, w->ox1, w->oy1})
+        if (!std::isfinite(v)) return CWO_ERR_INVALID;
+    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
+    if (p->flags != 0) return CWO_ERR_INVALID;
+    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
+    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
+        p->ny > kMaxN)
+        return CWO_ERR_UNSUPPORTED;
+    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    return CWO_OK;
+}
+
+cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresnel* w,
+                               const void* in, void* out, void* stream) {
+    if (!c) return CWO_ERR_INVALID;
+    cwo_status st = validate_sfresnel(p, w);
+    if (st != CWO_OK) return st;
+    if (!in || !out) return CWO_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = begin(c);
+    if (st != CWO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& ws = c->ws;
+    const Geometry g{p->nx, p->ny, 2 * p->nx, 2 * p->ny};
+    const float2* twx = twiddle_table(c, g.mx, s, &st);
+    if (!twx) return st;
+    const float2* twy = twiddle_table(c, g.my, s, &st);
+    if (!twy) return st;
+    float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    if (!buf) return st;
+    const size_t ntab = 2 * (size_t)(g.nx + g.ny);
+    float2* tabs = (float2*)ensure(c, ws, ws.fourier, sizeof(float2) * (ntab + g.mx + g.my), &st);
+    if (!tabs) return st;
+    double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * (size_t)(g.mx + g.my), &st);
+    if (!work) return st;
+    float2* hfac = tabs + ntab;
+    // the convolution kernel exp(i pi S d^2), S = p0 p1/(lambda z), is the Fresnel impulse
+    // response of pitch sqrt(p0 p1); its factors carry no constant
+    cwo::FresnelPlanes fp;
+    std::memset(&fp, 0, sizeof(fp));
+    fp.mx = g.mx;
+    fp.nx = g.nx;
+    fp.my = g.my;
+    fp.ny = g.ny;
+    fp.dx = std::sqrt(p->dx * w->dx1);
+    fp.dy = std::sqrt(p->dy * w->dy1);
+    fp.nz = 1;
+    fp.inv2lz[0] = 0.5 / (p->wavelength * p->z);
+    fp.cre[0] = 1.0;
+    fp.cim[0] = 0.0;
+    cwo::SfPlan sp;
+    sp.nx = g.nx;
+    sp.ny = g.ny;
+    sp.px0 = p->dx;
+    sp.py0 = p->dy;
+    sp.px1 = w->dx1;
+    sp.py1 = w->dy1;
+    sp.ox0 = w->ox0;
+    sp.oy0 = w->oy0;
+    sp.ox1 = w->ox1;
+    sp.oy1 = w->oy1;
+    sp.inv_lz = 1.0 / (p->wavelength * p->z);
+    fresnel_constant(p->dx, p->dy, p->wavelength, p->z, &sp.cre, &sp.cim);
+    CWO_HIP(c, timed(c, CWO_STAGE_TABLES, s, [&] {
+                const hipError_t e = cwo::launch_sf_tables(tabs, sp, s);
+                return e != hipSuccess ? e : cwo::launch_fresnel_planes(work, hfac, fp, s);
+            }));
+    CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
+                return cwo::launch_sf_row_fwd((const float2*)in, buf, g.nx, g.ny, tabs, twx, s);
+            }));
+    CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                return cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, 1, 0, hfac, hfac + g.mx,
+                                               cwo::Storage{}, twy, s);
+            }));
+    const float scale = 1.0f / ((float)g.mx * (float)g.my);
+    CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
+                return cwo::launch_sf_row_inv(buf, (float2*)out, g.nx, g.ny, scale, tabs, twx, s);
+            }));
+    return CWO_OK;
+}
+
 cwo_status cwo_asm_shifted(cwo_ctx* c, const cwo_params* p, const cwo_shift* sh, const void* in,
                            void* out, void* stream) {
     if (!c || !p || !sh) return CWO_ERR_INVALID;
@@ -951,6 +1038,10 @@ cwo_status cwo_profile_read(cwo_ctx* c, int32_t stage, double* total_ms, int64_t
 
 cwo_status cwo_check_params(const cwo_params* p, int32_t kind) {
     if (kind == CWO_FRESNEL_FOURIER) return validate_fourier(p);
+    if (kind == CWO_FRESNEL_SHIFTED) {
+        const cwo_sfresnel w{p ? p->dx : 1.0, p ? p->dy : 1.0, 0.0, 0.0, 0.0, 0.0};
+        return validate_sfresnel(p, &w);
+    }
     return validate(p, kind, true);
 }
 

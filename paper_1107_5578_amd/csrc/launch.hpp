@@ -140,4 +140,22 @@ hipError_t launch_fresnel_fourier(const float2* in, float2* out, float2* tabs,
                                   const FourierPlan& fp, const float2* twx, const float2* twy,
                                   hipStream_t s);
 
+// Shifted Fresnel diffraction (Sec. 2.1.3): parameters of the source and destination
+// chirp tables.
+struct SfPlan {
+    int nx, ny;
+    double px0, py0, px1, py1;  // source and destination pitch [m]
+    double ox0, oy0, ox1, oy1;  // window centres [m]
+    double inv_lz;              // 1/(lambda z)
+    double cre, cim;            // dx0 dy0 exp(i k z)/(i lambda z)
+};
+// tabs: 2 (nx + ny) complex64 (source chirps, then destination chirps with the constant).
+hipError_t launch_sf_tables(float2* tabs, const SfPlan& sp, hipStream_t s);
+// Padded row forward of the chirped field into scratch [ny][2nx].
+hipError_t launch_sf_row_fwd(const float2* in, float2* out, int nx, int ny, const float2* tabs,
+                             const float2* tw, hipStream_t s);
+// Row inverse of scratch [ny][2nx], crop, scale and destination chirp into out [ny][nx].
+hipError_t launch_sf_row_inv(const float2* in, float2* out, int nx, int ny, float scale,
+                             const float2* tabs, const float2* tw, hipStream_t s);
+
 }  // namespace cwo

@@ -28,6 +28,7 @@ CWO_ERR_NOTFOUND = -5
 ANGULAR = 1
 FRESNEL_CONV = 2
 FRESNEL_FOURIER = 3
+FRESNEL_SHIFTED = 4
 
 PREC_F32 = 0
 PREC_F16 = 1
@@ -89,6 +90,13 @@ class Shift(ctypes.Structure):
                 ("cy", ctypes.c_double), ("wy", ctypes.c_double)]
 
 
+class SFresnel(ctypes.Structure):
+    """cwo_sfresnel: destination pitch and the two window centres [m]."""
+    _fields_ = [("dx1", ctypes.c_double), ("dy1", ctypes.c_double),
+                ("ox0", ctypes.c_double), ("oy0", ctypes.c_double),
+                ("ox1", ctypes.c_double), ("oy1", ctypes.c_double)]
+
+
 SIGNATURES = {
     "cwo_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t]),
     "cwo_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -100,6 +108,9 @@ SIGNATURES = {
                                          ctypes.POINTER(Shift), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
     "cwo_band_limit": (ctypes.c_int32, [ctypes.POINTER(Params), ctypes.POINTER(Shift)]),
+    "cwo_fresnel_shifted": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                             ctypes.POINTER(SFresnel), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel_fourier": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel_fourier_pitch": (ctypes.c_int32, [ctypes.POINTER(Params),
@@ -258,6 +269,22 @@ class Context:
         fresnel_fourier_pitch(...)."""
         return self._propagate(self._lib.cwo_fresnel_fourier, FRESNEL_FOURIER, u, dx, dy,
                                wavelength, z, "f32", False, out, stream)
+
+    def fresnel_shifted(self, u, dx0=10e-6, dy0=None, dx1=10e-6, dy1=None, wavelength=633e-9,
+                        z=0.1, ox0=0.0, oy0=0.0, ox1=0.0, oy1=0.0, out=None, stream=None):
+        """Shifted Fresnel diffraction from a window of pitch (dx0, dy0) centred at
+        (ox0, oy0) to one of pitch (dx1, dy1) centred at (ox1, oy1) [m]."""
+        dy0 = dx0 if dy0 is None else dy0
+        dy1 = dx1 if dy1 is None else dy1
+        w = SFresnel(float(dx1), float(dy1), float(ox0), float(oy0), float(ox1), float(oy1))
+        lib = self._lib
+
+        def call(h, pp, a, b, s):
+            return lib.cwo_fresnel_shifted(h, pp, ctypes.byref(w), a, b, s)
+
+        call.__name__ = "cwo_fresnel_shifted"
+        return self._propagate(call, FRESNEL_SHIFTED, u, dx0, dy0, wavelength, z, "f32", False,
+                               out, stream)
 
     def asm_shifted(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, ox=0.0, oy=0.0,
                     cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None):

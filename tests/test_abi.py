@@ -152,3 +152,20 @@ def test_fresnel_fourier_params_and_pitch():
     q = cwo.make_params(8192, 64, 10e-6, z=0.1, kind=K)
     assert cwo.check_params(q, K) == cwo.CWO_ERR_UNSUPPORTED
     assert lib.cwo_fresnel_fourier(None, ctypes.byref(p), None, None, None) == cwo.CWO_ERR_INVALID
+
+
+def test_fresnel_shifted_params():
+    lib = cwo.load()
+    K = cwo.FRESNEL_SHIFTED
+    p = cwo.make_params(256, 128, 10e-6, 8e-6, 633e-9, 0.2, kind=K)
+    assert cwo.check_params(p, K) == cwo.CWO_OK
+    for b in [dict(z=0.0), dict(flags=1), dict(kind=2), dict(wavelength=-1.0)]:
+        q = cwo.make_params(64, 64, 10e-6, z=0.1, kind=K)
+        for k, v in b.items():
+            setattr(q, k, v)
+        assert cwo.check_params(q, K) == cwo.CWO_ERR_INVALID, b
+    q = cwo.make_params(64, 64, 10e-6, z=0.1, kind=K, precision="bf16")
+    assert cwo.check_params(q, K) == cwo.CWO_ERR_UNSUPPORTED
+    w = cwo.SFresnel(5e-6, 5e-6, 0.0, 0.0, 1e-3, 0.0)
+    assert lib.cwo_fresnel_shifted(None, ctypes.byref(p), ctypes.byref(w), None, None,
+                                   None) == cwo.CWO_ERR_INVALID
