@@ -147,6 +147,26 @@ typedef struct {
 cwo_status cwo_fresnel_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_sfresnel* window,
                                const void* in, void* out, void* hip_stream);
 
+/* Field epilogues of the paper's examples, n elements each, device pointers, ordered on
+ * the stream; n == 0 does nothing, a null pointer with n > 0 is CWO_ERR_INVALID.
+ *   cwo_intensity: out_f32[i] = re*re + im*im of in_c64[i] (Sec. 3.1), FP32, the two
+ *                  products and the sum rounded separately.
+ *   cwo_phase:     out_f32[i] = atan2(im, re) in [-pi, pi] (the kinoform, Sec. 7.1).
+ *   cwo_polar:     out_c64[i] = a * exp(i phase_f32[i]), a = amp_f32[i] or 1 if amp is
+ *                  null (a phase field back to a complex field, Sec. 7.1).
+ *   cwo_scale:     (v - min) * (top / (max - min)) over all n values (Sec. 3.1, Eq. norm),
+ *                  in FP32 in that order, 0 if max == min; out_u8 = 0 writes float32,
+ *                  out_u8 = 1 writes uint8 rounded to nearest (ties to even) and clamped to
+ *                  [0, 255] (then top <= 255). top must be finite and > 0. Scratch: a few KiB
+ *                  of partial minima and maxima held by the context. */
+cwo_status cwo_intensity(cwo_ctx* ctx, const void* in_c64, void* out_f32, size_t n,
+                         void* hip_stream);
+cwo_status cwo_phase(cwo_ctx* ctx, const void* in_c64, void* out_f32, size_t n, void* hip_stream);
+cwo_status cwo_polar(cwo_ctx* ctx, const void* phase_f32, const void* amp_f32, void* out_c64,
+                     size_t n, void* hip_stream);
+cwo_status cwo_scale(cwo_ctx* ctx, const void* in_f32, void* out, int32_t out_u8, float top,
+                     size_t n, void* hip_stream);
+
 /* Shifted angular spectrum method (Sec. 2.1.5, Eqs. shift_ang1 and shift_ang2): the
  * transfer function of cwo_asm times exp(i 2 pi (ox fx + oy fy)) and times the band-limit
  * functions Rect((fx - cx)/wx) Rect((fy - cy)/wy), Rect(t) = 1 for |t| <= 1/2. The linear

@@ -8,9 +8,10 @@ namespace cwo {
 
 // ---- column pass: FFT, transfer function, IFFT, crop --------------------------
 
-// Exact form, for any parameters: per bin in FP64, the propagating test s <= 1
-// evaluated with the same operations as the FP64 reference, sine/cosine of the
-// reduced phase in FP32.
+// Exact form, for any parameters: per bin in FP64, the propagating test s <= 1 evaluated
+// as lam*(p'*df) squared and summed, each operation rounded on its own (fused
+// multiply-adds are switched off, so the decision is that of the plain FP64 definition),
+// sine/cosine of the reduced phase in FP32.
 struct AsmH {
     double dfx, dfy;  // frequency pitches 1/(Mx dx), 1/(My dy)
     double lam;       // wavelength
@@ -20,23 +21,26 @@ struct AsmH {
         double ax2;
     };
     __device__ __forceinline__ Col column(int p) const {
+#pragma clang fp contract(off)
         const double pp = (double)(p < mx / 2 ? p : p - mx);
-        const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
-        return Col{__dmul_rn(ax, ax)};
+        const double ax = lam * (pp * dfx);
+        return Col{ax * ax};
     }
     struct Row {
         double ay2;
     };
     __device__ __forceinline__ Row row(int q) const {
+#pragma clang fp contract(off)
         const double qq = (double)(q < my / 2 ? q : q - my);
-        const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
-        return Row{__dmul_rn(ay, ay)};
+        const double ay = lam * (qq * dfy);
+        return Row{ay * ay};
     }
     __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
+#pragma clang fp contract(off)
         // s = (lambda*fx)^2 + (lambda*fy)^2 with fx = p'*dfx, evaluated without contraction
-        const double s = __dadd_rn(rw.ay2, c.ax2);
+        const double s = rw.ay2 + c.ax2;
         if (!(s <= 1.0)) return make_float2(0.f, 0.f);  // evanescent bin
-        const double t = zl * __dsqrt_rn(1.0 - s);       // revolutions
+        const double t = zl * sqrt(1.0 - s);             // revolutions
         const float r = (float)(t - rint(t));            // [-0.5, 0.5]
         return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
     }

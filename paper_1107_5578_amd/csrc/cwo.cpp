@@ -55,15 +55,16 @@ struct Workspace {
     Buffer ftab;                      // per-plane Fresnel factors of a z-stack chunk
     Buffer gsnum;                     // per-row error partials of the ping-pong iteration
     Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
-    Buffer fourier;                   // chirp tables of the Fresnel Fourier form
+    Buffer fourier;                   // chirp tables of the Fresnel Fourier and shifted forms
+    Buffer ework;                     // min/max partials of the scale epilogue
     std::list<FresnelEntry> fresnel;  // most recently used first
     size_t budget = 0;                // 0: unbounded (serving slots are bounded by admission)
     size_t held() const {
         return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes +
-               fourier.bytes;
+               fourier.bytes + ework.bytes;
     }
     void release() {
-        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier}) {
+        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier, &ework}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->bytes = 0;
@@ -651,6 +652,51 @@ void stop_serving(cwo_ctx* c) {
     if (c->worker.joinable()) c->worker.join();
 }
 
+// Fresnel Fourier form: sizes as the other kinds, z != 0, no flags, complex64 only.
+cwo_status validate_fourier(const cwo_params* p) {
+    if (!p) return CWO_ERR_INVALID;
+    if (p->kind != 0 && p->kind != CWO_FRESNEL_FOURIER) return CWO_ERR_INVALID;
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
+    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
+    if (p->flags != 0) return CWO_ERR_INVALID;
+    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
+    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
+        p->ny > kMaxN)
+        return CWO_ERR_UNSUPPORTED;
+    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    return CWO_OK;
+}
+
+// Shifted Fresnel: sizes as the other kinds (padded 2N), z != 0, no flags, complex64 only.
+cwo_status validate_sfresnel(const cwo_params* p, const cwo_sfresnel* w) {
+    if (!p || !w) return CWO_ERR_INVALID;
+    if (p->kind != 0 && p->kind != CWO_FRESNEL_SHIFTED) return CWO_ERR_INVALID;
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
+    if (!finite_pos(w->dx1) || !finite_pos(w->dy1)) return CWO_ERR_INVALID;
+    for (double v : {w->ox0, w->oy0, w->ox1, w->oy1})
+        if (!std::isfinite(v)) return CWO_ERR_INVALID;
+    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
+    if (p->flags != 0) return CWO_ERR_INVALID;
+    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
+    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
+        p->ny > kMaxN)
+        return CWO_ERR_UNSUPPORTED;
+    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
+    return CWO_OK;
+}
+
+// Epilogues: stream-ordered elementwise passes on the context's device.
+template <class F>
+cwo_status epilogue(cwo_ctx* c, size_t n, bool ok, F&& launch) {
+    if (!c || !ok) return CWO_ERR_INVALID;
+    if (n == 0) return CWO_OK;
+    std::lock_guard<std::mutex> lock(c->mu);
+    const cwo_status st = begin(c);
+    if (st != CWO_OK) return st;
+    CWO_HIP(c, launch());
+    return CWO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -767,21 +813,6 @@ cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* ou
     return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream);
 }
 
-// Fresnel Fourier form: sizes as the other kinds, z != 0, no flags, complex64 only.
-cwo_status validate_fourier(const cwo_params* p) {
-    if (!p) return CWO_ERR_INVALID;
-    if (p->kind != 0 && p->kind != CWO_FRESNEL_FOURIER) return CWO_ERR_INVALID;
-    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
-    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
-    if (p->flags != 0) return CWO_ERR_INVALID;
-    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
-    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
-        p->ny > kMaxN)
-        return CWO_ERR_UNSUPPORTED;
-    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
-    return CWO_OK;
-}
-
 cwo_status cwo_fresnel_fourier(cwo_ctx* c, const cwo_params* p, const void* in, void* out,
                                void* stream) {
     if (!c) return CWO_ERR_INVALID;
@@ -821,24 +852,6 @@ cwo_status cwo_fresnel_fourier_pitch(const cwo_params* p, double* dx2, double* d
     if (!dx2 || !dy2) return CWO_ERR_INVALID;
     *dx2 = p->wavelength * p->z / ((double)p->nx * p->dx);
     *dy2 = p->wavelength * p->z / ((double)p->ny * p->dy);
-    return CWO_OK;
-}
-
-// Shifted Fresnel: sizes as the other kinds (padded 2N), z != 0, no flags, complex64 only.
-cwo_status validate_sfresnel(const cwo_params* p, const cwo_sfresnel* w) {
-    if (!p || !w) return CWO_ERR_INVALID;
-    if (p->kind != 0 && p->kind != CWO_FRESNEL_SHIFTED) return CWO_ERR_INVALID;
-    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
-    if (!finite_pos(w->dx1) || !finite_pos(w->dy1)) return CWO_ERR_INVALID;
-    for (double v : {w->ox0, w->oy0, w->ox1, w->oy1})
-        if (!std::isfinite(v)) return CWO_ERR_INVALID;
-    if (!std::isfinite(p->z) || p->z == 0.0) return CWO_ERR_INVALID;
-    if (p->flags != 0) return CWO_ERR_INVALID;
-    if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
-    if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
-        p->ny > kMaxN)
-        return CWO_ERR_UNSUPPORTED;
-    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
     return CWO_OK;
 }
 
@@ -908,6 +921,43 @@ cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresn
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
                 return cwo::launch_sf_row_inv(buf, (float2*)out, g.nx, g.ny, scale, tabs, twx, s);
             }));
+    return CWO_OK;
+}
+
+cwo_status cwo_intensity(cwo_ctx* c, const void* in, void* out, size_t n, void* stream) {
+    return epilogue(c, n, n == 0 || (in && out), [&] {
+        return cwo::launch_intensity((const float2*)in, (float*)out, n, (hipStream_t)stream);
+    });
+}
+
+cwo_status cwo_phase(cwo_ctx* c, const void* in, void* out, size_t n, void* stream) {
+    return epilogue(c, n, n == 0 || (in && out), [&] {
+        return cwo::launch_phase((const float2*)in, (float*)out, n, (hipStream_t)stream);
+    });
+}
+
+cwo_status cwo_polar(cwo_ctx* c, const void* phase, const void* amp, void* out, size_t n,
+                     void* stream) {
+    return epilogue(c, n, n == 0 || (phase && out), [&] {
+        return cwo::launch_polar((const float*)phase, (const float*)amp, (float2*)out, n,
+                                 (hipStream_t)stream);
+    });
+}
+
+cwo_status cwo_scale(cwo_ctx* c, const void* in, void* out, int32_t out_u8, float top, size_t n,
+                     void* stream) {
+    const bool ok = (n == 0 || (in && out)) && (out_u8 == 0 || out_u8 == 1) &&
+                    std::isfinite(top) && top > 0.0f && (out_u8 == 0 || top <= 255.0f);
+    if (!c || !ok) return CWO_ERR_INVALID;
+    if (n == 0) return CWO_OK;
+    std::lock_guard<std::mutex> lock(c->mu);
+    cwo_status st = begin(c);
+    if (st != CWO_OK) return st;
+    float* work = (float*)ensure(c, c->ws, c->ws.ework, sizeof(float) * (4 + 2 * cwo::kRangeBlocks),
+                                 &st);
+    if (!work) return st;
+    CWO_HIP(c, cwo::launch_scale((const float*)in, n, top, out_u8 == 1, out, work,
+                                 (hipStream_t)stream));
     return CWO_OK;
 }
 

@@ -158,4 +158,12 @@ hipError_t launch_sf_row_fwd(const float2* in, float2* out, int nx, int ny, cons
 hipError_t launch_sf_row_inv(const float2* in, float2* out, int nx, int ny, float scale,
                              const float2* tabs, const float2* tw, hipStream_t s);
 
+// Field epilogues (Sec. 3.1, Sec. 7.1). launch_scale needs work of 4 + 2 * kRangeBlocks
+// floats (min, max and the factor first, then per-block partials).
+hipError_t launch_intensity(const float2* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_phase(const float2* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_polar(const float* phi, const float* amp, float2* out, size_t n, hipStream_t s);
+hipError_t launch_scale(const float* in, size_t n, float top, bool u8, void* out, float* work,
+                        hipStream_t s);
+
 }  // namespace cwo

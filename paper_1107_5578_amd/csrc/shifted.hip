@@ -15,12 +15,13 @@ namespace cwo {
 // cosine, which take revolutions.
 __device__ __forceinline__ float2 shift_factor(int p, int m, double df, double offset, double c,
                                                double w) {
-    const double f = __dmul_rn((double)(p < m / 2 ? p : p - m), df);
+#pragma clang fp contract(off)
+    const double f = (double)(p < m / 2 ? p : p - m) * df;
     if (w > 0.0) {
-        const double t = __ddiv_rn(__dsub_rn(f, c), w);
+        const double t = (f - c) / w;
         if (!(fabs(t) <= 0.5)) return make_float2(0.f, 0.f);
     }
-    const double u = __dmul_rn(offset, f);
+    const double u = offset * f;
     const float r = (float)(u - rint(u));
     return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }

@@ -49,12 +49,13 @@ struct AsmZExact {
     double dfx, dfy, lam;
     int mx, my;
     __device__ __forceinline__ double bin(int p, int q) const {
+#pragma clang fp contract(off)
         const double pp = (double)(p < mx / 2 ? p : p - mx);
         const double qq = (double)(q < my / 2 ? q : q - my);
-        const double ax = __dmul_rn(lam, __dmul_rn(pp, dfx));
-        const double ay = __dmul_rn(lam, __dmul_rn(qq, dfy));
-        const double s = __dadd_rn(__dmul_rn(ay, ay), __dmul_rn(ax, ax));
-        return (s <= 1.0) ? __dsqrt_rn(1.0 - s) : -1.0;
+        const double ax = lam * (pp * dfx);
+        const double ay = lam * (qq * dfy);
+        const double s = ay * ay + ax * ax;
+        return (s <= 1.0) ? sqrt(1.0 - s) : -1.0;
     }
     __device__ __forceinline__ float2 at(double qv, double zl, float) const {
         if (qv < 0.0) return make_float2(0.f, 0.f);

@@ -111,6 +111,15 @@ SIGNATURES = {
     "cwo_fresnel_shifted": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                              ctypes.POINTER(SFresnel), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_intensity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p]),
+    "cwo_phase": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p]),
+    "cwo_polar": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "cwo_scale": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_float, ctypes.c_size_t,
+                                   ctypes.c_void_p]),
     "cwo_fresnel_fourier": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel_fourier_pitch": (ctypes.c_int32, [ctypes.POINTER(Params),
@@ -269,6 +278,66 @@ class Context:
         fresnel_fourier_pitch(...)."""
         return self._propagate(self._lib.cwo_fresnel_fourier, FRESNEL_FOURIER, u, dx, dy,
                                wavelength, z, "f32", False, out, stream)
+
+    # -- epilogues (Sec. 3.1, Sec. 7.1) -------------------------------------
+    def _contig(self, t, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor" % (name, dtype))
+        return t
+
+    def intensity(self, u, stream=None):
+        """|u|^2 as a float32 tensor of u's shape."""
+        import torch
+        u = self._contig(u, torch.complex64, "u")
+        out = torch.empty(u.shape, dtype=torch.float32, device=u.device)
+        st = self._lib.cwo_intensity(self.handle, ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), u.numel(),
+                                     self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_intensity")
+        return out
+
+    def phase(self, u, stream=None):
+        """atan2(Im u, Re u) as a float32 tensor (the kinoform of u)."""
+        import torch
+        u = self._contig(u, torch.complex64, "u")
+        out = torch.empty(u.shape, dtype=torch.float32, device=u.device)
+        st = self._lib.cwo_phase(self.handle, ctypes.c_void_p(u.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), u.numel(),
+                                 self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_phase")
+        return out
+
+    def polar(self, phase, amp=None, stream=None):
+        """amp * exp(i phase) (amp = 1 if None) as a complex64 tensor."""
+        import torch
+        phase = self._contig(phase, torch.float32, "phase")
+        if amp is not None:
+            amp = self._contig(amp, torch.float32, "amp")
+            if amp.shape != phase.shape:
+                raise ValueError("amp must match phase")
+        out = torch.empty(phase.shape, dtype=torch.complex64, device=phase.device)
+        st = self._lib.cwo_polar(self.handle, ctypes.c_void_p(phase.data_ptr()),
+                                 ctypes.c_void_p(amp.data_ptr() if amp is not None else None),
+                                 ctypes.c_void_p(out.data_ptr()), phase.numel(),
+                                 self._stream(phase, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_polar")
+        return out
+
+    def scale(self, x, top=255.0, u8=False, stream=None):
+        """(x - min)/(max - min) * top as float32, or as uint8 codes when u8."""
+        import torch
+        x = self._contig(x, torch.float32, "x")
+        out = torch.empty(x.shape, dtype=torch.uint8 if u8 else torch.float32, device=x.device)
+        st = self._lib.cwo_scale(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), 1 if u8 else 0, float(top),
+                                 x.numel(), self._stream(x, stream))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_scale")
+        return out
 
     def fresnel_shifted(self, u, dx0=10e-6, dy0=None, dx1=10e-6, dy1=None, wavelength=633e-9,
                         z=0.1, ox0=0.0, oy0=0.0, ox1=0.0, oy1=0.0, out=None, stream=None):

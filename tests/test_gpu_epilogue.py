@@ -1,0 +1,114 @@
+"""GPU epilogues (cwo_intensity, cwo_scale, cwo_phase, cwo_polar) against the oracle.
+
+Intensity and the scale are FP32 with a fixed operation order, so on the same complex64
+input they are compared bit for bit, 8-bit codes included. Phase and polar use the FP32
+library functions: within 4e-7 (a few ulps of pi) of the FP64 values of the same input.
+The kinoform example of Sec. 7.1 runs end to end against the FP64 pipeline."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D, epilogues as P
+from paper_1107_5578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1107_5578_amd import cwo
+    c = cwo.Context(0)
+    yield c
+    c.close()
+
+
+def note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n", [1, 1000, 512 * 512 + 3])
+def test_intensity_and_scale_bit_exact(ctx, n):
+    import torch
+    rng = np.random.default_rng(n)
+    u = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    u[:: 97] = 0
+    note("epilogue n=%d" % n)
+    t = torch.from_numpy(u).cuda()
+    i = ctx.intensity(t)
+    torch.cuda.synchronize()
+    i_np = i.cpu().numpy()
+    assert np.array_equal(i_np.view(np.uint32), P.intensity(u).view(np.uint32))
+    s = ctx.scale(i).cpu().numpy()
+    q = ctx.scale(i, 255.0, u8=True).cpu().numpy()
+    assert np.array_equal(s.view(np.uint32), P.scale(i_np).view(np.uint32))
+    assert np.array_equal(q, P.scale_u8(i_np))
+    s1 = ctx.scale(i, 1.0).cpu().numpy()
+    assert np.array_equal(s1.view(np.uint32), P.scale(i_np, 1.0).view(np.uint32))
+
+
+def test_scale_degenerate_and_errors(ctx):
+    import torch
+    from paper_1107_5578_amd import cwo
+    c = torch.full((4096,), 2.5, dtype=torch.float32, device="cuda")
+    assert int(ctx.scale(c).count_nonzero()) == 0
+    assert int(ctx.scale(c, u8=True).count_nonzero()) == 0
+    for top, u8 in [(0.0, False), (math.inf, False), (300.0, True)]:
+        with pytest.raises(cwo.CwoError) as e:
+            ctx.scale(c, top, u8)
+        assert e.value.status == cwo.CWO_ERR_INVALID
+    empty = torch.empty(0, dtype=torch.float32, device="cuda")
+    assert ctx.scale(empty).numel() == 0
+
+
+def test_phase_and_polar(ctx):
+    import torch
+    rng = np.random.default_rng(9)
+    u = (rng.standard_normal(100000) + 1j * rng.standard_normal(100000)).astype(np.complex64)
+    u[:4] = np.array([complex(-1, 0.0), complex(-1, -0.0), 1j, -1j], dtype=np.complex64)
+    t = torch.from_numpy(u).cuda()
+    ph = ctx.phase(t)
+    torch.cuda.synchronize()
+    ref = P.phase(u)
+    err = np.max(np.abs(ph.cpu().numpy().astype(np.float64) - ref))
+    note("phase max err %.3e" % err)
+    assert err <= 4e-7
+    amp = torch.from_numpy(np.abs(u).astype(np.float32)).cuda()
+    back = ctx.polar(ph, amp)
+    one = ctx.polar(ph)
+    torch.cuda.synchronize()
+    refc = P.polar(ph.cpu().numpy(), amp.cpu().numpy())
+    e1 = np.max(np.abs(back.cpu().numpy() - refc) / np.maximum(amp.cpu().numpy(), 1e-30))
+    e2 = np.max(np.abs(one.cpu().numpy() - P.polar(ph.cpu().numpy())))
+    note("polar max rel err %.3e / %.3e" % (e1, e2))
+    assert e1 <= 4e-7 and e2 <= 4e-7
+    assert np.max(np.abs(back.cpu().numpy() - u) / np.maximum(np.abs(u), 1e-30)) <= 1e-6
+
+
+def test_kinoform_example(ctx):
+    # Sec. 7.1: random phase on an amplitude image, Fresnel conv by z, keep the phase,
+    # back to complex, propagate back by -z, intensity, 8-bit image
+    import torch
+    n, d, lam, z = 512, 10e-6, 633e-9, 0.1
+    amp = W.rectangles_amplitude(n, 71).astype(np.float64)
+    u = (amp * np.exp(1j * W.random_phase(n, 72))).astype(np.complex64)
+    t = torch.from_numpy(u).cuda()
+    k = ctx.phase(ctx.fresnel(t, d, d, lam, z))
+    rec = ctx.fresnel(ctx.polar(k), d, d, lam, -z)
+    img = ctx.scale(ctx.intensity(rec), 255.0, u8=True)
+    torch.cuda.synchronize()
+    k_ref = P.phase(D.fresnel(u, d, d, lam, z))
+    rec_ref = D.fresnel(P.polar(k_ref).astype(np.complex64), d, d, lam, -z)
+    img_ref = P.scale_u8(P.intensity(rec_ref.astype(np.complex64)))
+    dk = np.abs(np.angle(np.exp(1j * (k.cpu().numpy() - k_ref))))
+    diff = np.abs(img.cpu().numpy().astype(int) - img_ref.astype(int))
+    note("kinoform: phase diff mean %.3e q999 %.3e, 8-bit image max diff %d, differing %.2e" %
+         (dk.mean(), np.quantile(dk, 0.999), diff.max(), np.mean(diff > 0)))
+    # the phase of a near-zero sample is ill-conditioned: bound the bulk, not the maximum
+    assert dk.mean() <= 1e-5 and np.quantile(dk, 0.999) <= 1e-4
+    assert diff.max() <= 2 and np.mean(diff > 0) <= 1e-3
