@@ -97,6 +97,90 @@ def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm):
     return len(zs) * 1000.0 / ms, ms
 
 
+def time_call(torch, stream, fn, reps, warm):
+    """Milliseconds per call of fn over `reps` calls, HIP events on the launch stream."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def other_forms(ctx, torch, W, u, u_np, cfg, stream, with_oracle):
+    """The other diffraction forms and the epilogues on the same 2048^2 field: planes/s,
+    algorithmic bytes and GB/s (and the error against the oracle when it is run)."""
+    n = u.shape[0]
+    res = {}
+    out = torch.empty_like(u)
+
+    def rec(name, ms, alg_bytes, extra=None):
+        r = {"ms": round(ms, 4), "planes_per_s": round(1000.0 / ms, 1), "alg_bytes": alg_bytes,
+             "GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1)}
+        r.update(extra or {})
+        res[name] = r
+
+    # shifted angular spectrum, band-limited, far beyond the critical distance
+    z_bl = 3.0
+    from paper_1107_5578_amd import cwo
+    wx, wy = cwo.band_limit(n, n, cfg.pitch, cfg.pitch, cfg.wavelength, z_bl)
+    sh = (1.2e-3, -0.4e-3, 0.0, wx, 0.0, wy)
+    ms = time_call(torch, stream, lambda: ctx.asm_shifted(u, cfg.pitch, cfg.pitch, cfg.wavelength,
+                                                          z_bl, *sh, out=out), 50, 5)
+    extra = {"z_m": z_bl, "offset_m": [sh[0], sh[1]], "band_width_per_m": [wx, wy]}
+    if with_oracle:
+        from oracle import shifted_asm as S
+        ref = S.propagate(u_np, cfg.pitch, cfg.pitch, cfg.wavelength, z_bl, *sh)
+        extra["rel_l2_vs_oracle"] = float("%.3e" % rel_l2(out.cpu().numpy(), ref))
+    rec("asm_shifted", ms, 80 * n * n, extra)
+
+    # Fresnel, Fourier form: one unpadded FFT, in place on the output plane
+    ms = time_call(torch, stream, lambda: ctx.fresnel_fourier(u, cfg.pitch, cfg.pitch,
+                                                              cfg.wavelength, cfg.z, out=out), 100, 5)
+    extra = {"z_m": cfg.z}
+    if with_oracle:
+        from oracle import fresnel_fourier as F
+        ref = F.propagate(u_np, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+        extra["rel_l2_vs_oracle"] = float("%.3e" % rel_l2(out.cpu().numpy(), ref))
+    rec("fresnel_fourier", ms, 32 * n * n, extra)
+
+    # shifted Fresnel: destination pitch 1.5x, window moved off axis
+    p1 = 1.5 * cfg.pitch
+    offs = (0.0, 0.0, 2.0e-3, -1.0e-3)
+    ms = time_call(torch, stream, lambda: ctx.fresnel_shifted(u, cfg.pitch, cfg.pitch, p1, p1,
+                                                              cfg.wavelength, cfg.z, *offs, out=out),
+                   50, 5)
+    extra = {"z_m": cfg.z, "dst_pitch_m": p1, "dst_centre_m": [offs[2], offs[3]]}
+    if with_oracle:
+        from oracle import shifted_fresnel as SF
+        rows = [0, n // 3, n // 2, n - 1]
+        ref = SF.propagate(u_np, cfg.pitch, cfg.pitch, p1, p1, cfg.wavelength, cfg.z, *offs,
+                           rows=rows)
+        extra["rel_l2_vs_oracle_rows"] = float("%.3e" % rel_l2(out.cpu().numpy()[rows], ref))
+    rec("fresnel_shifted", ms, 80 * n * n, extra)
+
+    # epilogues on the propagated plane: intensity, then the 8-bit min-max image
+    def epi():
+        i = ctx.intensity(out)
+        return ctx.scale(i, 255.0, u8=True)
+
+    ms = time_call(torch, stream, epi, 100, 5)
+    rec("intensity_scale_u8", ms, 21 * n * n)
+    return res
+
+
+def rel_l2(y, ref):
+    import numpy as np
+    y = np.asarray(y, dtype=np.complex128)
+    ref = np.asarray(ref, dtype=np.complex128)
+    return float(np.linalg.norm((y - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
 def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 0.95)):
     """Serving: a stream of mixed requests (sizes 512..4096^2, ASM/Fresnel 50/50,
     z ~ U[0.01, 1] m, wavelength in {473, 532, 633} nm, 8 um pitch) through cwo_submit /
@@ -187,6 +271,8 @@ def main():
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--no-gs", action="store_true",
                     help="skip the ping-pong (GS) iteration measurement")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other diffraction forms and the epilogues")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (a plain copy "
                          "kernel of known traffic, to calibrate profiler byte counters)")
@@ -303,6 +389,10 @@ def main():
               "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
         del ta1, ta2, tu
 
+    forms = None
+    if not args.no_forms and args.kind == "asm" and n == cfg.n and args.precision == "f32":
+        forms = other_forms(ctx, torch, W, u, u_np, cfg, stream, not args.no_cpu_baseline)
+
     serve = None
     if args.serve_requests > 0 and args.kind == "asm" and n == cfg.n and args.precision == "f32":
         serve = serve_bench(cwo.Context, torch, W, dev, args.serve_requests)
@@ -335,6 +425,8 @@ def main():
         line["batched"] = batched
     if gs is not None:
         line["gs_pingpong"] = gs
+    if forms is not None:
+        line["other_forms"] = forms
     if serve is not None:
         line["serving"] = serve
     if not args.no_cpu_baseline:
