@@ -28,15 +28,16 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 struct FresnelKey {
     int mx, nx, my, ny;
     double dx, dy, lam, z;
+    bool unit;  // the shifted form's kernel factors: no constant, chirp pitches sqrt(p0 p1)
     bool operator==(const FresnelKey& o) const {
         return mx == o.mx && nx == o.nx && my == o.my && ny == o.ny && dx == o.dx && dy == o.dy &&
-               lam == o.lam && z == o.z;
+               lam == o.lam && z == o.z && unit == o.unit;
     }
 };
 
 struct FresnelEntry {
     FresnelKey key;
-    float2* h = nullptr;  // mx + my complex64: Hx (with C) then Hy
+    float2* h = nullptr;  // mx + my complex64: Hx (with C unless unit) then Hy
 };
 
 // A device buffer that only grows; growing waits for the device first because
@@ -305,16 +306,18 @@ cwo::FresnelPlanes fresnel_planes(const cwo_params* p, const Geometry& g, const 
 }
 
 // Fresnel factors of one plane, cached per parameter set.
-const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, const Geometry& g,
-                              hipStream_t s, cwo_status* st) {
-    FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z};
+// Transformed 1-D chirps of the Fresnel kernel, cached per parameter set (most recently
+// used first). unit: the shifted form's kernel (chirp pitch sqrt(p0 p1) passed as
+// dx, dy, no constant).
+const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hipStream_t s,
+                           cwo_status* st) {
     for (auto it = ws.fresnel.begin(); it != ws.fresnel.end(); ++it) {
         if (it->key == key) {
             ws.fresnel.splice(ws.fresnel.begin(), ws.fresnel, it);
             return ws.fresnel.front().h;
         }
     }
-    const size_t len = (size_t)(g.mx + g.my);
+    const size_t len = (size_t)(key.mx + key.my);
     double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len, st);
     if (!work) return nullptr;
     if (ws.fresnel.size() >= kFresnelCacheEntries) {
@@ -332,8 +335,22 @@ const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, co
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
-    const double z = p->z;
-    const cwo::FresnelPlanes fp = fresnel_planes(p, g, &z, 1);
+    cwo::FresnelPlanes fp;
+    std::memset(&fp, 0, sizeof(fp));
+    fp.mx = key.mx;
+    fp.nx = key.nx;
+    fp.my = key.my;
+    fp.ny = key.ny;
+    fp.dx = key.dx;
+    fp.dy = key.dy;
+    fp.nz = 1;
+    fp.inv2lz[0] = 0.5 / (key.lam * key.z);
+    if (key.unit) {
+        fp.cre[0] = 1.0;
+        fp.cim[0] = 0.0;
+    } else {
+        fresnel_constant(key.dx, key.dy, key.lam, key.z, &fp.cre[0], &fp.cim[0]);
+    }
     if (timed(c, CWO_STAGE_TABLES, s, [&] { return cwo::launch_fresnel_planes(work, e.h, fp, s); }) !=
         hipSuccess) {
         (void)hipFree(e.h);
@@ -342,6 +359,12 @@ const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, co
     }
     ws.fresnel.push_front(e);
     return e.h;
+}
+
+const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, const Geometry& g,
+                              hipStream_t s, cwo_status* st) {
+    const FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z, false};
+    return factor_table(c, ws, key, s, st);
 }
 
 cwo_status begin(cwo_ctx* c) {
@@ -392,9 +415,11 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
             }));
     if (kind == CWO_ANGULAR && shift) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
+        float* masks = (float*)ensure(c, ws, ws.fourier, sizeof(float) * (size_t)(g.mx + g.my), &st);
+        if (!masks) return st;
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_asm_shifted((float2*)buf, g.ny, g.my, g.mx, a, *shift,
-                                                       twy, s);
+                                                       masks, twy, s);
                 }));
     } else if (kind == CWO_ANGULAR) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
@@ -873,26 +898,15 @@ cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresn
     if (!twy) return st;
     float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
     if (!buf) return st;
-    const size_t ntab = 2 * (size_t)(g.nx + g.ny);
-    float2* tabs = (float2*)ensure(c, ws, ws.fourier, sizeof(float2) * (ntab + g.mx + g.my), &st);
+    float2* tabs = (float2*)ensure(c, ws, ws.fourier, sizeof(float2) * 2 * (size_t)(g.nx + g.ny),
+                                   &st);
     if (!tabs) return st;
-    double2* work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * (size_t)(g.mx + g.my), &st);
-    if (!work) return st;
-    float2* hfac = tabs + ntab;
     // the convolution kernel exp(i pi S d^2), S = p0 p1/(lambda z), is the Fresnel impulse
     // response of pitch sqrt(p0 p1); its factors carry no constant
-    cwo::FresnelPlanes fp;
-    std::memset(&fp, 0, sizeof(fp));
-    fp.mx = g.mx;
-    fp.nx = g.nx;
-    fp.my = g.my;
-    fp.ny = g.ny;
-    fp.dx = std::sqrt(p->dx * w->dx1);
-    fp.dy = std::sqrt(p->dy * w->dy1);
-    fp.nz = 1;
-    fp.inv2lz[0] = 0.5 / (p->wavelength * p->z);
-    fp.cre[0] = 1.0;
-    fp.cim[0] = 0.0;
+    const FresnelKey key{g.mx, g.nx, g.my, g.ny, std::sqrt(p->dx * w->dx1),
+                         std::sqrt(p->dy * w->dy1), p->wavelength, p->z, true};
+    const float2* hfac = factor_table(c, ws, key, s, &st);
+    if (!hfac) return st;
     cwo::SfPlan sp;
     sp.nx = g.nx;
     sp.ny = g.ny;
@@ -906,10 +920,7 @@ cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresn
     sp.oy1 = w->oy1;
     sp.inv_lz = 1.0 / (p->wavelength * p->z);
     fresnel_constant(p->dx, p->dy, p->wavelength, p->z, &sp.cre, &sp.cim);
-    CWO_HIP(c, timed(c, CWO_STAGE_TABLES, s, [&] {
-                const hipError_t e = cwo::launch_sf_tables(tabs, sp, s);
-                return e != hipSuccess ? e : cwo::launch_fresnel_planes(work, hfac, fp, s);
-            }));
+    CWO_HIP(c, timed(c, CWO_STAGE_TABLES, s, [&] { return cwo::launch_sf_tables(tabs, sp, s); }));
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
                 return cwo::launch_sf_row_fwd((const float2*)in, buf, g.nx, g.ny, tabs, twx, s);
             }));
