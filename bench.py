@@ -364,6 +364,27 @@ def main():
         batched["zstack_1024x64"] = {"planes_per_s": round(c3_pps, 1), "ms_per_stack": round(c3_ms, 4),
                                      "workload": "1024x1024 speckle, 4um, 633nm, 64 z in [0.05, 0.2] m"}
         del u3
+        # 64 independent fields at one distance: one cwo_batch (one launch per pass) vs the
+        # same 64 propagations as plain calls
+        batched["independent_fields"] = {}
+        for ni in (n, 512):
+            fields = [torch.from_numpy(W.uniform_random_field(ni, 800 + k)).to(dev) for k in range(64)]
+            outs = [torch.empty_like(f) for f in fields]
+            kw = dict(dx=cfg.pitch, dy=cfg.pitch, wavelength=cfg.wavelength, z=cfg.z)
+            jobs = [("asm", f, o, kw) for f, o in zip(fields, outs)]
+            b_ms = time_call(torch, stream, lambda: ctx.batch(jobs), 5, 2)
+
+            def plain():
+                for f, o in zip(fields, outs):
+                    ctx.asm(f, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=o)
+
+            p_ms = time_call(torch, stream, plain, 5, 2)
+            batched["independent_fields"]["%d" % ni] = {
+                "planes_per_s": round(64 * 1000.0 / b_ms, 1),
+                "plain_planes_per_s": round(64 * 1000.0 / p_ms, 1),
+                "vs_plain": round(p_ms / b_ms, 3),
+                "workload": "64 independent %dx%d uniform random fields, one z" % (ni, ni)}
+            del fields, outs
 
     gs = None
     if not args.no_gs and args.kind == "asm" and n == cfg.n and args.precision == "f32":

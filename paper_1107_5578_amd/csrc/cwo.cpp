@@ -537,13 +537,92 @@ cwo_status validate_jobs(const cwo_job* jobs, int njobs) {
 }
 
 // Consecutive jobs on the same field and geometry run as one z-stack; the rest singly.
+// Identical parameters (distance included) on another field: such jobs run as one batch
+// per pass (complex64 storage; FP16 storage scales each field by its own range).
+bool same_params(const cwo_job& a, const cwo_job& b) {
+    return a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx && a.p.dy == b.p.dy &&
+           a.p.wavelength == b.p.wavelength && a.p.z == b.p.z && a.p.kind == b.p.kind &&
+           a.p.precision == CWO_PREC_F32 && b.p.precision == CWO_PREC_F32 && a.p.flags == b.p.flags;
+}
+
+// Jobs [i, j) with identical parameters, one batch per pass, in chunks of at most kZChunk
+// planes that fit the budget. Every field is read by the first pass before the last pass
+// writes any output, so a batch must not read another batch member's output.
+cwo_status batch_locked(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int n, hipStream_t s) {
+    cwo_status st = CWO_OK;
+    const cwo_params* p = &jobs[0].p;
+    const Geometry g = geometry(p);
+    const float2* twx = twiddle_table(c, g.mx, s, &st);
+    if (!twx) return st;
+    const float2* twy = twiddle_table(c, g.my, s, &st);
+    if (!twy) return st;
+    const float2* h = nullptr;
+    if (p->kind == CWO_FRESNEL_CONV) {
+        h = fresnel_factors(c, ws, p, g, s, &st);
+        if (!h) return st;
+    }
+    const size_t plane = (size_t)g.ny * g.mx;
+    int chunk = std::min(n, cwo::kZChunk);
+    if (ws.budget) {
+        const size_t other = ws.held() - ws.scratch.bytes;
+        const size_t fit = ws.budget > other ? (ws.budget - other) / (sizeof(float2) * plane) : 0;
+        if (fit == 0) return CWO_ERR_NOMEM;
+        chunk = (int)std::min<size_t>((size_t)chunk, fit);
+    }
+    float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * plane * (size_t)chunk, &st);
+    if (!buf) return st;
+    const float scale = 1.0f / ((float)g.mx * (float)g.my);
+    const cwo::AsmScalars a = asm_scalars(p, g, p->z);
+    for (int k0 = 0; k0 < n; k0 += chunk) {
+        const int nb = std::min(chunk, n - k0);
+        cwo::InTable ins;
+        cwo::OutTable outs;
+        for (int k = 0; k < cwo::kZChunk; ++k) {
+            ins.in[k] = k < nb ? (const float2*)jobs[k0 + k].in : nullptr;
+            outs.out[k] = k < nb ? (float2*)jobs[k0 + k].out : nullptr;
+        }
+        CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
+                    return cwo::launch_row_fwd_tab(ins, buf, g.nx, g.ny, g.mx, nb, plane, twx, s);
+                }));
+        CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                    return p->kind == CWO_ANGULAR
+                               ? cwo::launch_col_asm(buf, g.ny, g.my, g.mx, nb, plane, a, twy, s)
+                               : cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, nb, plane, h,
+                                                         h + g.mx, cwo::Storage{}, twy, s);
+                }));
+        CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
+                    return cwo::launch_row_inv_tab(buf, outs, g.nx, g.ny, g.mx, nb, plane, scale,
+                                                   twx, s);
+                }));
+    }
+    return CWO_OK;
+}
+
+// Length of the run of jobs from i with identical parameters whose inputs are all
+// different and none of which reads another member's output.
+int batch_run(const cwo_job* jobs, int i, int njobs) {
+    int j = i + 1;
+    while (j < njobs && j - i < cwo::kZChunk && same_params(jobs[i], jobs[j])) {
+        bool ok = true;
+        for (int k = i; k < j && ok; ++k)
+            ok = jobs[k].in != jobs[j].in && jobs[k].out != jobs[j].in && jobs[k].in != jobs[j].out &&
+                 jobs[k].out != jobs[j].out;
+        if (!ok) break;
+        ++j;
+    }
+    return j - i;
+}
+
 cwo_status run_jobs(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int njobs, hipStream_t s) {
     cwo_status st = CWO_OK;
     int i = 0;
     while (i < njobs) {
         int j = i + 1;
         while (j < njobs && same_group(jobs[i], jobs[j])) ++j;
-        if (j - i == 1) {
+        if (j - i == 1 && batch_run(jobs, i, njobs) > 1) {
+            j = i + batch_run(jobs, i, njobs);
+            st = batch_locked(c, ws, jobs + i, j - i, s);
+        } else if (j - i == 1) {
             st = propagate_locked(c, ws, &jobs[i].p, jobs[i].p.kind, jobs[i].in, jobs[i].out, s);
         } else {
             std::vector<double> z;

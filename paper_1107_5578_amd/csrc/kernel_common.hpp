@@ -87,17 +87,6 @@ __device__ __forceinline__ ItemRange xcd_items(int bid, int nblocks, int items) 
     return ItemRange{bid, nblocks, items};
 }
 
-// ---- output plane addressing of the row inverse ------------------------------
-
-struct OutStrided {
-    float2* out;
-    size_t plane;
-    __device__ __forceinline__ float2* operator()(int k) const { return out + k * plane; }
-};
-struct OutTable {
-    float2* out[kZChunk];
-    __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
-};
 
 // ---- host helpers -----------------------------------------------------------
 

@@ -128,6 +128,36 @@ struct FresnelPlanes {
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s);
 
+// Independent fields of one geometry in one launch per pass: the row forward pass reads
+// plane k from ins.in[k] into scratch plane k, the row inverse writes plane k to
+// outs.out[k] (batch <= kZChunk; complex64).
+// Plane addressing: equally spaced planes, or one pointer per plane (input of the row
+// forward pass, output of the row inverse).
+struct InStrided {
+    const float2* in;
+    size_t plane;
+    __device__ __forceinline__ const float2* operator()(int k) const { return in + k * plane; }
+};
+struct InTable {
+    const float2* in[kZChunk];
+    __device__ __forceinline__ const float2* operator()(int k) const { return in[k]; }
+};
+
+struct OutStrided {
+    float2* out;
+    size_t plane;
+    __device__ __forceinline__ float2* operator()(int k) const { return out + k * plane; }
+};
+struct OutTable {
+    float2* out[kZChunk];
+    __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
+};
+hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
+                              size_t out_plane, const float2* tw, hipStream_t s);
+hipError_t launch_row_inv_tab(const float2* in, const OutTable& outs, int nx, int ny, int mx,
+                              int batch, size_t in_plane, float scale, const float2* tw,
+                              hipStream_t s);
+
 // Fresnel diffraction in Fourier form (Sec. 2.1.2): parameters of the chirp tables.
 struct FourierPlan {
     int nx, ny;

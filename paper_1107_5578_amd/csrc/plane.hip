@@ -36,11 +36,11 @@ struct RowScale {
     const float* dyn;
 };
 
-template <int M, bool HALF, class ST>
-__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __restrict__ in,
+template <int M, bool HALF, class ST, class IN>
+__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(IN ins,
                                                                   typename ST::E* __restrict__ out,
-                                                                  int nx, int ny, size_t in_plane,
-                                                                  size_t out_plane, RowScale sc,
+                                                                  int nx, int ny, size_t out_plane,
+                                                                  RowScale sc,
                                                                   const float2* __restrict__ tw) {
     using C = RowCfg<M>;
     constexpr int E = C::E, T = C::T;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
     const int sub = tid / T, j = tid % T;
     const int row = blockIdx.x * C::RPB + sub;
     const bool valid = row < ny;
-    const float2* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * nx;
+    const float2* src = ins(blockIdx.y) + (size_t)(valid ? row : 0) * nx;
     TwCache<M, E> twc;
     if constexpr (E == 16) twc.load(j, tw);
     float2 v[1][E];
@@ -79,12 +79,11 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(const float2* __
 
 // Persistent form: a grid of resident blocks walks the rows (block b takes row groups
 // b, b + G, ...) and issues the next group's loads before transforming the current one.
-template <int M, bool HALF, class ST>
-__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(const float2* __restrict__ in,
+template <int M, bool HALF, class ST, class IN>
+__global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(IN ins,
                                                                      typename ST::E* __restrict__ out,
                                                                      int nx, int ny, int batch,
-                                                                     size_t in_plane, size_t out_plane,
-                                                                     RowScale sc,
+                                                                     size_t out_plane, RowScale sc,
                                                                      const float2* __restrict__ tw) {
     using C = RowCfg<M>;
     constexpr int E = C::E, T = C::T;
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(const float2*
         const int w = g * C::RPB + sub;
         const bool ok = w < rows;
         const int pl = ok ? w / ny : 0, row = ok ? w - pl * ny : 0;
-        const float2* src = in + pl * in_plane + (size_t)row * nx;
+        const float2* src = ins(pl) + (size_t)row * nx;
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const int x = j + r * T;
@@ -234,10 +233,10 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class ST>
-static hipError_t launch_row_fwd_t(const float2* in, void* out, int nx, int ny, int mx, int batch,
-                                   size_t in_plane, size_t out_plane, RowScale sc,
-                                   const float2* tw, hipStream_t s) {
+template <class ST, class IN>
+static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int mx, int batch,
+                                   size_t out_plane, RowScale sc, const float2* tw,
+                                   hipStream_t s) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
     // persistent form with prefetch where rows are long enough to fill whole blocks
@@ -246,9 +245,9 @@ static hipError_t launch_row_fwd_t(const float2* in, void* out, int nx, int ny, 
             if constexpr (RowCfg<MM>::E == 16) {
                 using C = RowCfg<MM>;
                 const int groups = (ny * batch + C::RPB - 1) / C::RPB;
-                auto k = k_row_fwd_pf<MM, true, ST>;
+                auto k = k_row_fwd_pf<MM, true, ST, IN>;
                 hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
-                                   0, s, in, (SE*)out, nx, ny, batch, in_plane, out_plane, sc, tw);
+                                   0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
             }
         });
         return hipGetLastError();
@@ -257,11 +256,11 @@ static hipError_t launch_row_fwd_t(const float2* in, void* out, int nx, int ny, 
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
         if (half)
-            hipLaunchKernelGGL((k_row_fwd<MM, true, ST>), grid, dim3(C::THREADS), 0, s, in,
-                               (SE*)out, nx, ny, in_plane, out_plane, sc, tw);
+            hipLaunchKernelGGL((k_row_fwd<MM, true, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
+                               (SE*)out, nx, ny, out_plane, sc, tw);
         else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_row_fwd<MM, false, ST>), grid, dim3(C::THREADS), 0, s, in,
-                               (SE*)out, nx, ny, in_plane, out_plane, sc, tw);
+            hipLaunchKernelGGL((k_row_fwd<MM, false, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
+                               (SE*)out, nx, ny, out_plane, sc, tw);
         else
             return hipErrorInvalidValue;
     });
@@ -273,16 +272,22 @@ hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, i
                           hipStream_t s) {
     const RowScale sc{st.in_scale, st.dyn_scale};
     switch (st.prec) {
-        case 0: return launch_row_fwd_t<StF32>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
-        case 1: return launch_row_fwd_t<StF16>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
-        case 2: return launch_row_fwd_t<StBF16>(in, out, nx, ny, mx, batch, in_plane, out_plane, sc, tw, s);
+        case 0: return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
+        case 1: return launch_row_fwd_t<StF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
+        case 2: return launch_row_fwd_t<StBF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
                           size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s) {
-    return launch_row_fwd_t<StF32>(in, out, nx, ny, mx, batch, in_plane, out_plane,
+    return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane,
+                                   RowScale{1.0f, nullptr}, tw, s);
+}
+
+hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
+                              size_t out_plane, const float2* tw, hipStream_t s) {
+    return launch_row_fwd_t<StF32>(ins, out, nx, ny, mx, batch, out_plane,
                                    RowScale{1.0f, nullptr}, tw, s);
 }
 
@@ -398,6 +403,12 @@ hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx,
                           hipStream_t s) {
     return launch_row_inv_impl(in, OutStrided{out, out_plane}, nx, ny, mx, batch, in_plane, scale,
                                tw, s);
+}
+
+hipError_t launch_row_inv_tab(const float2* in, const OutTable& outs, int nx, int ny, int mx,
+                              int batch, size_t in_plane, float scale, const float2* tw,
+                              hipStream_t s) {
+    return launch_row_inv_impl(in, outs, nx, ny, mx, batch, in_plane, scale, tw, s);
 }
 
 hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,

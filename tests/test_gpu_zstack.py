@@ -179,3 +179,37 @@ def test_batch_validation_before_launch(ctx):
     assert e.value.status == cwo.CWO_ERR_INVALID
     torch.cuda.synchronize()
     assert torch.count_nonzero(o).item() == 0   # nothing ran
+
+
+@pytest.mark.parametrize("n,kind", [(256, "asm"), (512, "fresnel"), (64, "asm")])
+def test_batch_independent_fields(ctx, n, kind):
+    # identical parameters on different fields run as one batch per pass: every output
+    # equals the single call bit for bit (same kernels, one more grid dimension)
+    import torch
+    note("batch of independent %s fields %d^2" % (kind, n))
+    fields = [torch.from_numpy(W.uniform_random_field(n, 700 + k)).cuda() for k in range(11)]
+    outs = [torch.empty_like(f) for f in fields]
+    kw = dict(dx=8e-6, dy=8e-6, wavelength=532e-9, z=0.07)
+    ctx.batch([(kind, f, o, kw) for f, o in zip(fields, outs)])
+    torch.cuda.synchronize()
+    single = ctx.asm if kind == "asm" else ctx.fresnel
+    for f, o in zip(fields, outs):
+        ref = single(f, 8e-6, 8e-6, 532e-9, 0.07)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref)
+    check(outs[3].cpu().numpy(), D.propagate(fields[3].cpu().numpy(), kind, 8e-6, 8e-6, 532e-9,
+                                             0.07), "batched field 3")
+
+
+def test_batch_chained_jobs_keep_their_order(ctx):
+    # a job that reads another job's output is not batched with it
+    import torch
+    u = torch.from_numpy(W.uniform_random_field(128, 5)).cuda()
+    a = torch.empty_like(u)
+    b = torch.empty_like(u)
+    kw = dict(dx=8e-6, dy=8e-6, wavelength=532e-9, z=0.05)
+    ctx.batch([("asm", u, a, kw), ("asm", a, b, kw)])
+    torch.cuda.synchronize()
+    ref = ctx.asm(ctx.asm(u, 8e-6, 8e-6, 532e-9, 0.05), 8e-6, 8e-6, 532e-9, 0.05)
+    torch.cuda.synchronize()
+    assert torch.equal(b, ref)
