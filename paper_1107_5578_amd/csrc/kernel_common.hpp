@@ -29,11 +29,12 @@ struct RowCfg {
 // stores, one 16-byte LDS slot per element pair); PAIRS column pairs per block.
 template <int M>
 struct ColCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
+    // 16 values per thread at every length (T = M/16 threads per column pair, up to 512
+    // at M = 8192, whose two columns then take 139 KB of LDS: one block per CU)
+    static constexpr int E = 16;
     static constexpr int T = M / E;
-    // two columns per thread, except at M = 8192 where 32 values per column already
-    // fill the register budget; the two columns share one LDS buffer (split exchange)
-    static constexpr int P = (M == 8192) ? 1 : 2;
+    // two adjacent columns per thread: 16-byte accesses, shared twiddles
+    static constexpr int P = 2;
     static constexpr bool SPLIT = false;
     static constexpr int LDS_PAIR = (SPLIT ? 1 : P) * lds_elems<M>();  // float2 entries per pair
     static constexpr int BY_THR = (T >= 256) ? 1 : 256 / T;
@@ -50,7 +51,7 @@ struct ColCfg {
 // inverse transform runs on a copy, so one column per thread.
 template <int M>
 struct ZColCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
+    static constexpr int E = 16;
     static constexpr int T = M / E;
     static constexpr int P = 1;
     static constexpr int LDS_PAIR = lds_elems<M>();
