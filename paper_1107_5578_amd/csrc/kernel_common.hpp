@@ -19,7 +19,7 @@ namespace cwo {
 // Row passes: one transform per thread group of T = M/E threads, RPB rows per block.
 template <int M>
 struct RowCfg {
-    static constexpr int E = (M == 512 || M == 8192) ? 32 : 16;
+    static constexpr int E = 16;
     static constexpr int T = M / E;
     static constexpr int RPB = (T >= 256) ? 1 : 256 / T;  // rows per block
     static constexpr int THREADS = T * RPB;

@@ -240,7 +240,7 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
     // persistent form with prefetch where rows are long enough to fill whole blocks
-    if (half && mx >= 1024 && mx != 8192) {
+    if (half && mx >= 1024) {
         CWO_DISPATCH_M(mx, {
             if constexpr (RowCfg<MM>::E == 16) {
                 using C = RowCfg<MM>;
@@ -362,7 +362,7 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
                                    const float2* tw, hipStream_t s) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
-    if (half && mx >= 1024 && mx != 8192) {
+    if (half && mx >= 1024) {
         CWO_DISPATCH_M(mx, {
             if constexpr (RowCfg<MM>::E == 16) {
                 using C = RowCfg<MM>;
