@@ -128,7 +128,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     const int pair = tid / T, j = tid % T;
     float2* my_lds = lds + pair * C::LDS_PAIR;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     const int ntiles = (mx + C::COLS - 1) / C::COLS;
     const int it = xcd_remap(blockIdx.x, gridDim.x);
     const int pl = it / ntiles, tile = it - pl * ntiles;
@@ -153,8 +153,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     typename HF::Col hc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
-    if constexpr (E == 16) fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
-    else fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, tw);
+    fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const typename HF::Row hr = hf.row(j + r * T);
@@ -165,8 +164,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
             v[p][r] = cmul(v[p][r], h);
         }
     }
-    if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
-    else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
+    fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;

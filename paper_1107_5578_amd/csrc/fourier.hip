@@ -59,7 +59,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_ff_row(const float2* in,
     const bool valid = row < ny;
     const int rr = valid ? row : 0;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     const float2 py = prey[rr];
     const float2* src = in + (size_t)rr * M;
     float2 v[1][E];
@@ -68,8 +68,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_ff_row(const float2* in,
         const int x = j + r * T;
         v[0][r] = cmul(src[x], cmul(prex[x], py));
     }
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
-    else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
         float2* dst = out + (size_t)row * M;
 #pragma unroll
@@ -92,7 +91,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     const int col = active ? col0 : 0;
     float2* base = buf + col;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -100,8 +99,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int p = 0; p < P; ++p) v[p][r] = t.e[p];
     }
-    if constexpr (E == 16) fft<M, E, P, FWD>(v, lds + pair * C::LDS_PAIR, j, twc);
-    else fft<M, E, P, FWD>(v, lds + pair * C::LDS_PAIR, j, tw);
+    fft<M, E, P, FWD>(v, lds + pair * C::LDS_PAIR, j, twc);
     float2 px[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) px[p] = postx[col + p];

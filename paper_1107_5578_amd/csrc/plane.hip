@@ -52,7 +52,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(IN ins,
     const bool valid = row < ny;
     const float2* src = ins(blockIdx.y) + (size_t)(valid ? row : 0) * nx;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -68,8 +68,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(IN ins,
 #pragma unroll
         for (int r = 0; r < E; ++r) v[0][r] = make_float2(v[0][r].x * f, v[0][r].y * f);
     }
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
-    else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
         typename ST::E* dst = out + blockIdx.y * out_plane + (size_t)row * M;
 #pragma unroll
@@ -145,12 +144,11 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
     const bool valid = row < ny;
     const typename ST::E* src = in + blockIdx.y * in_plane + (size_t)(valid ? row : 0) * M;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[0][r] = valid ? ST::dec(src[j + r * T]) : make_float2(0.f, 0.f);
-    if constexpr (E == 16) fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
-    else fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
         float2* dst = outs(blockIdx.y) + (size_t)row * nx;
 #pragma unroll
@@ -242,7 +240,7 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
     // persistent form with prefetch where rows are long enough to fill whole blocks
     if (half && mx >= 1024) {
         CWO_DISPATCH_M(mx, {
-            if constexpr (RowCfg<MM>::E == 16) {
+            if constexpr (MM >= 1024) {
                 using C = RowCfg<MM>;
                 const int groups = (ny * batch + C::RPB - 1) / C::RPB;
                 auto k = k_row_fwd_pf<MM, true, ST, IN>;
@@ -364,7 +362,7 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
     using SE = typename ST::E;
     if (half && mx >= 1024) {
         CWO_DISPATCH_M(mx, {
-            if constexpr (RowCfg<MM>::E == 16) {
+            if constexpr (MM >= 1024) {
                 using C = RowCfg<MM>;
                 const int groups = (ny * batch + C::RPB - 1) / C::RPB;
                 auto k = k_row_inv_pf<MM, true, OUT, ST>;

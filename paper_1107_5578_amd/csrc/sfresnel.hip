@@ -62,7 +62,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_sf_row_fwd(
     const bool valid = row < ny;
     const int rr = valid ? row : 0;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     const float2 py = prey[rr];
     const float2* src = in + (size_t)rr * nx;
     float2 v[1][E];
@@ -71,8 +71,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_sf_row_fwd(
         const int x = j + r * T;
         v[0][r] = (r < E / 2) ? cmul(src[x], cmul(prex[x], py)) : make_float2(0.f, 0.f);
     }
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
-    else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
         float2* dst = out + (size_t)row * M;
 #pragma unroll
@@ -94,13 +93,12 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_sf_row_inv(
     const bool valid = row < ny;
     const int rr = valid ? row : 0;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     const float2* src = in + (size_t)rr * M;
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[0][r] = src[j + r * T];
-    if constexpr (E == 16) fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
-    else fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, tw);
+    fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
     if (!valid) return;
     const float2 py = posty[row];
     float2* dst = out + (size_t)row * nx;

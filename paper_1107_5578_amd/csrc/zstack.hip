@@ -128,11 +128,10 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
     float2* my_lds = lds + sub * C::LDS_PAIR;
     double* my_kb = kbl + sub * M;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     float2 v[1][E];
     zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
-    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    fft<M, E, 1, FWD>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) my_kb[j + r * T] = zs.h.bin(col, j + r * T);
     for (int k = 0; k < zs.nz; ++k) {
@@ -141,13 +140,7 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
         float2 w[1][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(my_kb[j + r * T], zl, c0));
-        if constexpr (E == 16) {
-            fft<M, E, 1, INV>(w, my_lds, j, twc);
-        } else {
-            const float2* twk = tw;  // opaque per plane: twiddles are reloaded, not kept live
-            asm volatile("" : "+s"(twk));
-            fft<M, E, 1, INV>(w, my_lds, j, twk);
-        }
+        fft<M, E, 1, INV>(w, my_lds, j, twc);
         zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
     }
 }
@@ -167,24 +160,17 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
     const int col = active ? col0 : 0;
     float2* my_lds = lds + sub * C::LDS_PAIR;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     float2 v[1][E];
     zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
-    if constexpr (E == 16) fft<M, E, 1, FWD>(v, my_lds, j, twc);
-    else fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    fft<M, E, 1, FWD>(v, my_lds, j, twc);
     for (int k = 0; k < zs.nz; ++k) {
         const float2* hk = zs.h + (size_t)k * zs.stride;
         const float2 hx = hk[col];
         float2 w[1][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], cmul(hx, hk[zs.mx + j + r * T]));
-        if constexpr (E == 16) {
-            fft<M, E, 1, INV>(w, my_lds, j, twc);
-        } else {
-            const float2* twk = tw;
-            asm volatile("" : "+s"(twk));
-            fft<M, E, 1, INV>(w, my_lds, j, twk);
-        }
+        fft<M, E, 1, INV>(w, my_lds, j, twc);
         zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
     }
 }
@@ -208,7 +194,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     const int pair = tid / T, j = tid % T;
     float2* my_lds = lds + pair * C::LDS_PAIR;
     TwCache<M, E> twc;
-    if constexpr (E == 16) twc.load(j, tw);
+    twc.load(j, tw);
     const int ntiles = (ny + C::COLS - 1) / C::COLS;
     auto item = [&](int it) {
         const int pl = it / ntiles, tile = it - pl * ntiles;
@@ -222,8 +208,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int p = 0; p < P; ++p) v[p][r] = t.e[p];
         }
-        if constexpr (E == 16) fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
-        else fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, tw);
+        fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
         if (active) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -237,7 +222,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
             }
         }
     };
-    if constexpr (HALF && E == 16) {
+    if constexpr (HALF) {
         const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, ntiles * batch);
         for (int it = ir.first; it < ir.end; it += ir.step) item(it);
     } else {
@@ -257,7 +242,7 @@ hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny
         const int items = (ny + C::COLS - 1) / C::COLS * zc.nz;
         if (half) {
             auto k = k_row_inv_t<MM, true, OutTable>;
-            const int g = C::E == 16 ? resident_blocks(k, C::THREADS, items) : items;
+            const int g = resident_blocks(k, C::THREADS, items);
             hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, zbuf, t, nx, ny, zc.nz, zplane,
                                scale, tw);
         } else {
