@@ -385,6 +385,36 @@ def main():
                 "vs_plain": round(p_ms / b_ms, 3),
                 "workload": "64 independent %dx%d uniform random fields, one z" % (ni, ni)}
             del fields, outs
+        # the same work captured once into a HIP graph and replayed (launch overhead and
+        # host work paid once): the 1024^2 x 64 z-stack, 64 independent 512^2 fields in one
+        # cwo_batch, and 64 plain 512^2 calls
+        graph = {}
+        u3 = torch.from_numpy(W.field_for(c3)).to(dev)
+        o3 = torch.empty((64,) + tuple(u3.shape), dtype=torch.complex64, device=dev)
+        f512 = [torch.from_numpy(W.uniform_random_field(512, 830 + k)).to(dev) for k in range(64)]
+        o512 = [torch.empty_like(f) for f in f512]
+        kw = dict(dx=cfg.pitch, dy=cfg.pitch, wavelength=cfg.wavelength, z=cfg.z)
+        jobs = [("asm", f, o, kw) for f, o in zip(f512, o512)]
+        cases = {
+            "zstack_1024x64": (lambda: ctx.zstack(u3, z3, c3.pitch, c3.pitch, c3.wavelength, out=o3), 64),
+            "independent_512x64": (lambda: ctx.batch(jobs), 64),
+            "plain_512x64": (lambda: [ctx.asm(f, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z,
+                                              out=o) for f, o in zip(f512, o512)], 64),
+        }
+        for name, (fn, planes) in cases.items():
+            fn()
+            torch.cuda.synchronize()
+            eager_ms = time_call(torch, stream, fn, 20, 2)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            graph_ms = time_call(torch, torch.cuda.current_stream(dev), g.replay, 20, 2)
+            graph[name] = {"eager_planes_per_s": round(planes * 1000.0 / eager_ms, 1),
+                           "graph_planes_per_s": round(planes * 1000.0 / graph_ms, 1),
+                           "graph_vs_eager": round(eager_ms / graph_ms, 3)}
+            del g
+        batched["graph_replay"] = graph
+        del u3, o3, f512, o512
 
     gs = None
     if not args.no_gs and args.kind == "asm" and n == cfg.n and args.precision == "f32":

@@ -27,6 +27,11 @@
  * after enqueueing. Calls on one context share its scratch memory: serialise them
  * (one stream, or external synchronisation). cwo_submit / cwo_poll are thread-safe.
  *
+ * Graph capture: once a call with the same parameters (and, for z-stacks and batches, the
+ * same plane count) has run on a context, a propagation call only enqueues kernels on its
+ * stream, so it can be captured into a HIP graph and replayed; the first call allocates
+ * scratch and tables and must run outside the capture. Profiling must be off.
+ *
  * Errors: every call returns a cwo_status. Parameters are validated before anything is
  * launched. A device error makes the context return CWO_ERR_DEVICE from then on.
  * NaN or Inf inside field data is not checked and propagates.
