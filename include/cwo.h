@@ -196,6 +196,24 @@ cwo_status cwo_asm_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_shift* s
  * Host only; validates p like cwo_asm. */
 cwo_status cwo_band_limit(const cwo_params* p, cwo_shift* shift);
 
+/* Schedule of one parameter set, as picked by cwo_autotune. */
+typedef struct {
+    int32_t row_form;     /* row passes: 1 a resident grid that prefetches the next rows,
+                             2 one row group per block, 0 the default choice */
+    int32_t zchunk;       /* planes per z-stack launch (0: single-plane calls) */
+    float us_per_plane;   /* the best measured time */
+} cwo_tuning;
+
+/* Autotuner: runs the candidate schedules of this parameter set (row-pass form, and for
+ * nz > 1 the z-stack chunk size) on the given buffers, times each on the stream with HIP
+ * events (the call synchronises the stream), and keeps the fastest in the context for
+ * (kind, nx, ny, precision, flags, nz); later cwo_asm / cwo_fresnel calls (nz = 1) and
+ * z-stacks of nz planes with those parameters use it. Results do not depend on the
+ * schedule. in: complex64 [ny][nx]; out: complex64 [nz][ny][nx], overwritten; p->z is used
+ * for every plane. best may be null. Not thread-safe with other calls on the context. */
+cwo_status cwo_autotune(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const void* in, void* out,
+                        void* hip_stream, cwo_tuning* best);
+
 /* z-stack: one field propagated to nz distances, the paper's 3-D field built by stacking
  * 2-D propagations (Sec. 2.3, Diffract3D). p->kind selects CWO_ANGULAR or
  * CWO_FRESNEL_CONV (0 is CWO_ERR_INVALID here); p->z is ignored; z is a HOST array of nz

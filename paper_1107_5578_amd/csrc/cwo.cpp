@@ -10,6 +10,7 @@
 #include <deque>
 #include <list>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -91,6 +92,16 @@ struct Slot {
 
 }  // namespace
 
+// Schedule picked by cwo_autotune for one parameter set (the distance does not change the
+// work, so it is not part of the key; nz = 1 is the single-plane call).
+struct TuneKey {
+    int kind, nx, ny, precision, flags, nz;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(kind, nx, ny, precision, flags, nz) <
+               std::tie(o.kind, o.nx, o.ny, o.precision, o.flags, o.nz);
+    }
+};
+
 struct cwo_ctx {
     int device = 0;
     size_t budget = 0;
@@ -119,6 +130,9 @@ struct cwo_ctx {
     std::vector<hipEvent_t> spare;
     double prof_ms[CWO_STAGE_COUNT] = {};
     int64_t prof_n[CWO_STAGE_COUNT] = {};
+    // schedules picked by cwo_autotune (the serving thread reads them too)
+    std::mutex tmu;
+    std::map<TuneKey, cwo_tuning> tuned;
 };
 
 namespace {
@@ -367,6 +381,23 @@ const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, co
     return factor_table(c, ws, key, s, st);
 }
 
+TuneKey tune_key(const cwo_params* p, int kind, int nz) {
+    return TuneKey{kind, p->nx, p->ny, p->precision, (int)p->flags, nz};
+}
+
+// The tuned schedule of a parameter set ({0, 0, 0}: none, the defaults apply).
+cwo_tuning tuned_for(cwo_ctx* c, const cwo_params* p, int kind, int nz) {
+    std::lock_guard<std::mutex> g(c->tmu);
+    auto it = c->tuned.find(tune_key(p, kind, nz));
+    return it == c->tuned.end() ? cwo_tuning{0, 0, 0.0f} : it->second;
+}
+
+void set_tuned(cwo_ctx* c, const TuneKey& k, const cwo_tuning* t) {
+    std::lock_guard<std::mutex> g(c->tmu);
+    if (t) c->tuned[k] = *t;
+    else c->tuned.erase(k);
+}
+
 cwo_status begin(cwo_ctx* c) {
     if (c->sticky != CWO_OK) return c->sticky;
     if (hipSetDevice(c->device) != hipSuccess) return dev_fail(c);
@@ -393,6 +424,7 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
     }
     cwo::Storage sto;  // complex64: no intermediate scaling, 1/(Mx My) at the end
     sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);  // power of two: exact
+    sto.row_form = tuned_for(c, p, kind, 1).row_form;
     if (p->precision != CWO_PREC_F32) {
         // FP16/BF16 storage: 2^-floor(log2(Mx)/2) before the row transform, 1/My in the
         // column pass, the rest of 1/Mx at the end (all powers of two); FP16 also scales
@@ -465,6 +497,8 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
     const size_t len = (size_t)(g.mx + g.my);
     // chunk size: the shared spectrum and all planes of a chunk within the budget
     int zc = std::min(nz, cwo::kZChunk);
+    const cwo_tuning tune = tuned_for(c, p, kind, nz);
+    if (tune.zchunk > 0) zc = std::min(zc, tune.zchunk);
     if (ws.budget) {
         const size_t fres = kind == CWO_FRESNEL_CONV ? sizeof(float2) * len : 0;
         const size_t per_plane = sizeof(float2) * plane + fres;
@@ -486,7 +520,8 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
         if (!work) return st;
     }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
-                return cwo::launch_row_fwd((const float2*)in, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
+                return cwo::launch_row_fwd((const float2*)in, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s,
+                                           tune.row_form);
             }));
     const float scale = 1.0f / ((float)g.mx * (float)g.my);
     for (int k0 = 0; k0 < nz; k0 += zc) {
@@ -1074,6 +1109,72 @@ cwo_status cwo_band_limit(const cwo_params* p, cwo_shift* sh) {
         return 2.0 / (p->wavelength * std::sqrt(t * t + 1.0));
     };
     *sh = cwo_shift{0.0, 0.0, 0.0, width(g.mx, p->dx), 0.0, width(g.my, p->dy)};
+    return CWO_OK;
+}
+
+cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void* in, void* out,
+                        void* stream, cwo_tuning* best) {
+    if (!c || !p || !in || !out || nz < 1) return CWO_ERR_INVALID;
+    const int kind = p->kind;
+    cwo_status st = validate(p, kind, nz == 1);
+    if (st != CWO_OK) return st;
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = begin(c);
+    if (st != CWO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Geometry g = geometry(p);
+    const bool half = !(p->flags & CWO_FLAG_NOPAD);
+    std::vector<int> forms = (half && g.mx >= 1024) ? std::vector<int>{1, 2} : std::vector<int>{0};
+    std::vector<int> chunks{0};
+    if (nz > 1) {
+        chunks.clear();
+        for (int k : {2, 4, 8, 16, 32, cwo::kZChunk})
+            if (k < nz || k == cwo::kZChunk) chunks.push_back(std::min(k, nz));
+    }
+    const TuneKey key = tune_key(p, kind, nz);
+    std::vector<double> zs((size_t)nz, p->z);
+    std::vector<void*> outs((size_t)nz);
+    const size_t plane_bytes = sizeof(float2) * (size_t)p->nx * p->ny;
+    for (int k = 0; k < nz; ++k) outs[k] = (char*)out + k * plane_bytes;
+    auto run = [&]() {
+        return nz == 1 ? propagate_locked(c, c->ws, p, kind, in, out, s)
+                       : zstack_locked(c, c->ws, p, kind, zs.data(), nz, in, outs.data(), s);
+    };
+    hipEvent_t a = take_event(c), b = take_event(c);
+    cwo_tuning found{0, 0, 0.0f};
+    float best_ms = -1.0f;
+    for (int f : forms) {
+        for (int zc : chunks) {
+            const cwo_tuning cand{f, zc, 0.0f};
+            set_tuned(c, key, &cand);
+            st = run();  // warm-up: allocations and tables
+            if (st != CWO_OK) break;
+            constexpr int kReps = 3;
+            if (hipEventRecord(a, s) != hipSuccess) { st = dev_fail(c); break; }
+            for (int r = 0; r < kReps && st == CWO_OK; ++r) st = run();
+            if (st != CWO_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                st = dev_fail(c);
+                break;
+            }
+            ms /= kReps;
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                found = cwo_tuning{f, zc, (float)(1000.0 * ms / nz)};
+            }
+        }
+        if (st != CWO_OK) break;
+    }
+    c->spare.push_back(a);
+    c->spare.push_back(b);
+    if (st != CWO_OK) {
+        set_tuned(c, key, nullptr);
+        return st;
+    }
+    set_tuned(c, key, &found);
+    if (best) *best = found;
     return CWO_OK;
 }
 

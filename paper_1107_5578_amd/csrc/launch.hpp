@@ -47,6 +47,7 @@ struct Storage {
     float col_scale = 1.0f;
     float out_scale = 1.0f;
     const float* dyn_inv = nullptr;
+    int row_form = 0;  // row passes: 0 default, 1 persistent with prefetch, 2 one group per block
 };
 
 constexpr int kRangeBlocks = 1024;
@@ -76,7 +77,8 @@ hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, i
 
 // in: batch planes of [ny][nx] (plane stride in_plane elements); out: [ny][mx] per plane
 hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
-                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s);
+                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s,
+                          int row_form = 0);
 
 // buf: batch planes of [ny][mx], column transform of length my (my = ny or 2*ny)
 hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,

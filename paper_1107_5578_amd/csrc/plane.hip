@@ -234,11 +234,12 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
 template <class ST, class IN>
 static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int mx, int batch,
                                    size_t out_plane, RowScale sc, const float2* tw,
-                                   hipStream_t s) {
+                                   hipStream_t s, int form = 0) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
     // persistent form with prefetch where rows are long enough to fill whole blocks
-    if (half && mx >= 1024) {
+    // (form 2 asks for one row group per block)
+    if (half && mx >= 1024 && form != 2) {
         CWO_DISPATCH_M(mx, {
             if constexpr (MM >= 1024) {
                 using C = RowCfg<MM>;
@@ -270,17 +271,18 @@ hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, i
                           hipStream_t s) {
     const RowScale sc{st.in_scale, st.dyn_scale};
     switch (st.prec) {
-        case 0: return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
-        case 1: return launch_row_fwd_t<StF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
-        case 2: return launch_row_fwd_t<StBF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s);
+        case 0: return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
+        case 1: return launch_row_fwd_t<StF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
+        case 2: return launch_row_fwd_t<StBF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
-                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s) {
+                          size_t in_plane, size_t out_plane, const float2* tw, hipStream_t s,
+                          int row_form) {
     return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane,
-                                   RowScale{1.0f, nullptr}, tw, s);
+                                   RowScale{1.0f, nullptr}, tw, s, row_form);
 }
 
 hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
@@ -357,10 +359,10 @@ hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size
 template <class OUT, class ST>
 static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int ny, int mx,
                                    int batch, size_t in_plane, float scale, const float* dyn_inv,
-                                   const float2* tw, hipStream_t s) {
+                                   const float2* tw, hipStream_t s, int form = 0) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
-    if (half && mx >= 1024) {
+    if (half && mx >= 1024 && form != 2) {
         CWO_DISPATCH_M(mx, {
             if constexpr (MM >= 1024) {
                 using C = RowCfg<MM>;
@@ -416,13 +418,16 @@ hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, i
     switch (st.prec) {
         case 0:
             return launch_row_inv_t<OutStrided, StF32>(in, o, nx, ny, mx, batch, in_plane,
-                                                       st.out_scale, st.dyn_inv, tw, s);
+                                                       st.out_scale, st.dyn_inv, tw, s,
+                                                       st.row_form);
         case 1:
             return launch_row_inv_t<OutStrided, StF16>(in, o, nx, ny, mx, batch, in_plane,
-                                                       st.out_scale, st.dyn_inv, tw, s);
+                                                       st.out_scale, st.dyn_inv, tw, s,
+                                                       st.row_form);
         case 2:
             return launch_row_inv_t<OutStrided, StBF16>(in, o, nx, ny, mx, batch, in_plane,
-                                                        st.out_scale, st.dyn_inv, tw, s);
+                                                        st.out_scale, st.dyn_inv, tw, s,
+                                                       st.row_form);
     }
     return hipErrorInvalidValue;
 }

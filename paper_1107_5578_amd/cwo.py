@@ -97,6 +97,12 @@ class SFresnel(ctypes.Structure):
                 ("ox1", ctypes.c_double), ("oy1", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    """cwo_tuning: the schedule picked by cwo_autotune."""
+    _fields_ = [("row_form", ctypes.c_int32), ("zchunk", ctypes.c_int32),
+                ("us_per_plane", ctypes.c_float)]
+
+
 SIGNATURES = {
     "cwo_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t]),
     "cwo_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -125,6 +131,9 @@ SIGNATURES = {
     "cwo_fresnel_fourier_pitch": (ctypes.c_int32, [ctypes.POINTER(Params),
                                                    ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_double)]),
+    "cwo_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(Tuning)]),
     "cwo_zstack": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -369,6 +378,24 @@ class Context:
         return self._propagate(call, ANGULAR, u, dx, dy, wavelength, z, "f32", nopad, out,
                                stream)
 
+
+    def autotune(self, u, nz=1, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, kind="asm",
+                 precision="f32", nopad=False, stream=None):
+        """Pick and keep the fastest schedule for this parameter set (cwo_autotune);
+        returns (row_form, zchunk, us_per_plane)."""
+        import torch
+        u = self._field(u)
+        ny, nx = u.shape
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        p = make_params(nx, ny, dx, dy, wavelength, z, k, precision, nopad)
+        out = torch.empty((int(nz), ny, nx), dtype=torch.complex64, device=u.device)
+        t = Tuning()
+        st = self._lib.cwo_autotune(self.handle, ctypes.byref(p), int(nz),
+                                    ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    self._stream(u, stream), ctypes.byref(t))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_autotune")
+        return t.row_form, t.zchunk, t.us_per_plane
 
     def zstack(self, u, z, dx=10e-6, dy=None, wavelength=633e-9, kind="asm", precision="f32",
                nopad=False, out=None, stream=None):

@@ -169,3 +169,10 @@ def test_fresnel_shifted_params():
     w = cwo.SFresnel(5e-6, 5e-6, 0.0, 0.0, 1e-3, 0.0)
     assert lib.cwo_fresnel_shifted(None, ctypes.byref(p), ctypes.byref(w), None, None,
                                    None) == cwo.CWO_ERR_INVALID
+
+
+def test_autotune_null_context():
+    p = cwo.make_params(64, 64, 10e-6, z=0.1, kind=cwo.ANGULAR)
+    t = cwo.Tuning()
+    assert cwo.load().cwo_autotune(None, ctypes.byref(p), 1, None, None, None,
+                                   ctypes.byref(t)) == cwo.CWO_ERR_INVALID
