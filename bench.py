@@ -429,20 +429,27 @@ def main():
         ta2 = torch.from_numpy(a2).to(dev)
         tu = torch.from_numpy(u0).to(dev)
         g = W.GS_2048
-        ctx.gs(tu.clone(), ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=5)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        errs = ctx.gs(tu, ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=200)
-        b.record(stream)
-        torch.cuda.synchronize()
-        gms = a.elapsed_time(b)
-        e = errs.cpu().numpy()
-        gs = {"workload": "2048x2048 rectangles targets 0.1 m apart, 8um, 532nm, 200 iterations",
-              "ms_total": round(gms, 3), "ms_per_iteration": round(gms / 200, 4),
-              "propagations_per_s": round(400 * 1000.0 / gms, 1),
-              "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
+        gs = {"workload": "2048x2048 rectangles targets 0.1 m apart, 8um, 532nm, 200 iterations"}
+        for prec in ("f32", "f16", "bf16"):
+            # storage of the padded spectrum between passes; arithmetic stays FP32
+            tp = tu.clone()
+            ctx.gs(tp.clone(), ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=5,
+                   precision=prec)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            errs = ctx.gs(tp, ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=200,
+                          precision=prec)
+            b.record(stream)
+            torch.cuda.synchronize()
+            gms = a.elapsed_time(b)
+            e = errs.cpu().numpy()
+            gs[prec + "_storage"] = {
+                "ms_total": round(gms, 3), "ms_per_iteration": round(gms / 200, 4),
+                "propagations_per_s": round(400 * 1000.0 / gms, 1),
+                "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
+            del tp
         del ta1, ta2, tu
 
     forms = None

@@ -241,7 +241,12 @@ cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip
  * exit. a1, a2: device float32 [ny][nx] amplitudes. errors: device float32[iterations]
  * receiving E_k, or NULL. p->kind must be 0 or CWO_ANGULAR. Each propagation is one
  * column pass plus one fused row pass (inverse row FFT, crop, constraint, re-pad,
- * forward row FFT). Scratch: ny * 2nx complex64, plus iterations * ny doubles for E_k. */
+ * forward row FFT). p->precision picks the storage of the padded spectrum between the
+ * passes (complex64, or FP16 / BF16 pairs with the power-of-two scalings of cwo_asm; the
+ * FP16 form also scales each field entering a forward transform by 2^-e, e the binary
+ * exponent of its largest component: u, then a2 and a1); arithmetic, u and E_k stay
+ * FP32 (E_k's sums FP64). Low precision needs the padded form (no CWO_FLAG_NOPAD).
+ * Scratch: ny * 2nx stored values, plus iterations * ny doubles for E_k. */
 cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* hip_stream);
 

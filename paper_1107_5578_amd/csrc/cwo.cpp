@@ -1206,7 +1206,7 @@ cwo_status cwo_batch(cwo_ctx* c, const cwo_job* jobs, int32_t njobs, void* strea
 cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* stream) {
     if (!c || !a1 || !a2 || !u || iterations < 0) return CWO_ERR_INVALID;
-    cwo_status st = validate(p, CWO_ANGULAR);
+    cwo_status st = validate(p, CWO_ANGULAR, true);
     if (st != CWO_OK) return st;
     std::lock_guard<std::mutex> lock(c->mu);
     if ((st = begin(c)) != CWO_OK) return st;
@@ -1217,7 +1217,7 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    float2* spec = (float2*)ensure(c, c->ws, c->ws.scratch, sizeof(float2) * (size_t)g.ny * g.mx, &st);
+    void* spec = ensure(c, c->ws, c->ws.scratch, elem_bytes(p->precision) * (size_t)g.ny * g.mx, &st);
     if (!spec) return st;
     double* num = nullptr;
     if (errors) {
@@ -1226,26 +1226,56 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
         if (!num) return st;
     }
     const cwo::AsmScalars fwd = asm_scalars(p, g, p->z), back = asm_scalars(p, g, -p->z);
-    const float scale = 1.0f / ((float)g.mx * (float)g.my);
     float2* field = (float2*)u;
+    const size_t count = (size_t)g.ny * g.nx;
+    // Storage of the padded spectrum; low precision takes the scalings of a single
+    // propagation, and FP16 also scales each field entering a forward transform by 2^-e,
+    // e the exponent of its largest component: the start field, then the amplitude that
+    // constrained it (|a u/|u|| = a).
+    cwo::Storage sto;
+    cwo::GsScale g2, g1;  // row passes after the +z and the -z column pass
+    sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
+    g2.scale = g1.scale = sto.out_scale;
+    if (p->precision != CWO_PREC_F32) {
+        sto.prec = g2.prec = g1.prec = p->precision == CWO_PREC_F16_STORAGE ? 1 : 2;
+        const int kx = ilog2(g.mx) / 2;
+        sto.in_scale = g2.fwd_scale = g1.fwd_scale = std::ldexp(1.0f, -kx);
+        sto.col_scale = 1.0f / (float)g.my;
+        sto.out_scale = g2.scale = g1.scale = std::ldexp(1.0f, kx) / (float)g.mx;
+        if (sto.prec == 1) {
+            const size_t w = 2 + cwo::kRangeBlocks;
+            float* rw = (float*)ensure(c, c->ws, c->ws.rwork, sizeof(float) * 3 * w, &st);
+            if (!rw) return st;
+            float *ru = rw, *ra2 = rw + w, *ra1 = rw + 2 * w;
+            CWO_HIP(c, cwo::launch_range_scale(field, count, ru, s));
+            CWO_HIP(c, cwo::launch_range_scale(a2, count, ra2, s));
+            CWO_HIP(c, cwo::launch_range_scale(a1, count, ra1, s));
+            sto.dyn_scale = ru;
+            g2.dyn_fwd = ra2;
+            g1.dyn_inv = ra2 + 1;
+            g1.dyn_fwd = ra1;
+            g2.dyn_inv = ru + 1;  // first iteration; ra1 + 1 from the second on
+        }
+    }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
-                return cwo::launch_row_fwd(field, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s);
+                return cwo::launch_row_fwd(field, spec, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s);
             }));
     for (int k = 0; k < iterations; ++k) {
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, fwd, twy, s);
+                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, fwd, sto, twy, s);
                 }));
         double* nk = num ? num + (size_t)k * g.ny : nullptr;
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_GS, s, [&] {
-                    return cwo::launch_row_gs(spec, a2, nullptr, nk, g.nx, g.ny, g.mx, scale, twx, s);
+                    return cwo::launch_row_gs(spec, a2, nullptr, nk, g.nx, g.ny, g.mx, g2, twx, s);
                 }));
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, back, twy, s);
+                    return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, back, sto, twy, s);
                 }));
         float2* dst = (k == iterations - 1) ? field : nullptr;
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_GS, s, [&] {
-                    return cwo::launch_row_gs(spec, a1, dst, nullptr, g.nx, g.ny, g.mx, scale, twx, s);
+                    return cwo::launch_row_gs(spec, a1, dst, nullptr, g.nx, g.ny, g.mx, g1, twx, s);
                 }));
+        if (g1.dyn_fwd) g2.dyn_inv = g1.dyn_fwd + 1;
     }
     if (errors) {
         double* den = num + (size_t)iterations * g.ny;

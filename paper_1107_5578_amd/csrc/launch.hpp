@@ -54,6 +54,8 @@ constexpr int kRangeBlocks = 1024;
 // work[0] = 2^-e, work[1] = 2^e with e = the binary exponent of max(|re|, |im|) over the
 // n values; work must hold 2 + kRangeBlocks floats.
 hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream_t s);
+// the same for a real array (e = the exponent of max |a|)
+hipError_t launch_range_scale(const float* in, size_t n, float* work, hipStream_t s);
 
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s);
 
@@ -104,14 +106,25 @@ hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my
 hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
                             size_t zplane, float scale, const float2* tw, hipStream_t s);
 
-// Ping-pong iteration row kernel. For each of the ny rows of spec ([ny][mx], the output
-// of a column pass): inverse row FFT, keep the first nx values scaled by `scale`, replace
-// each value u by a*u/|u| (a where u == 0) with a from amp ([ny][nx] float32), and, if
-// num is not null, store the row's FP64 sum of (|u| - a)^2 in num[row]. Then either
-// (out == nullptr) zero-pad and forward row FFT back into spec, or write the constrained
-// field to out ([ny][nx]).
-hipError_t launch_row_gs(float2* spec, const float* amp, float2* out, double* num, int nx, int ny,
-                         int mx, float scale, const float2* tw, hipStream_t s);
+// Scalings of the ping-pong row kernel for spectra stored as Storage::prec (0 complex64,
+// 1 FP16, 2 BF16): the inverse row transform is multiplied by scale * (*dyn_inv), and
+// the constrained field by fwd_scale * (*dyn_fwd) before the forward transform; null
+// dyn pointers count as 1.
+struct GsScale {
+    int prec = 0;
+    float scale = 1.0f;
+    const float* dyn_inv = nullptr;
+    float fwd_scale = 1.0f;
+    const float* dyn_fwd = nullptr;
+};
+// Ping-pong iteration row kernel. For each of the ny rows of spec ([ny][mx] in the
+// storage of gsc.prec, the output of a column pass): inverse row FFT, keep the first nx
+// values scaled as gsc says, replace each value u by a*u/|u| (a where u == 0) with a from
+// amp ([ny][nx] float32), and, if num is not null, store the row's FP64 sum of
+// (|u| - a)^2 in num[row]. Then either (out == nullptr) zero-pad and forward row FFT back
+// into spec, or write the constrained field to out ([ny][nx] complex64).
+hipError_t launch_row_gs(void* spec, const float* amp, float2* out, double* num, int nx, int ny,
+                         int mx, const GsScale& gsc, const float2* tw, hipStream_t s);
 // errors[k] = sqrt(sum_rows num[k*ny + row] / sum(amp^2)), k < iters; den_work holds 1 double.
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
                             int nx, int ny, int iters, hipStream_t s);

@@ -434,15 +434,17 @@ hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, i
 
 // ---- range of a field for FP16 storage -----------------------------------------
 
-// per-block maximum of |re|, |im| over a grid-strided range
-__global__ __launch_bounds__(256) void k_absmax_partial(const float2* __restrict__ in, size_t n,
+__device__ __forceinline__ float absmax(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+__device__ __forceinline__ float absmax(float v) { return fabsf(v); }
+
+// per-block maximum of |re|, |im| (of |a| for a real array) over a grid-strided range
+template <class T>
+__global__ __launch_bounds__(256) void k_absmax_partial(const T* __restrict__ in, size_t n,
                                                         float* __restrict__ partial) {
     __shared__ float red[256];
     float m = 0.f;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const float2 v = in[i];
-        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
-    }
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        m = fmaxf(m, absmax(in[i]));
     red[threadIdx.x] = m;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
@@ -477,14 +479,23 @@ __global__ __launch_bounds__(256) void k_absmax_final(const float* __restrict__ 
     }
 }
 
-hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream_t s) {
-    const int blocks = (int)((n + 256 * 16 - 1) / (256 * 16)) < kRangeBlocks
-                           ? (int)((n + 256 * 16 - 1) / (256 * 16))
-                           : kRangeBlocks;
-    const int nb = blocks < 1 ? 1 : blocks;
-    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, s, in, n, work + 2);
+namespace {
+template <class T>
+hipError_t range_scale_t(const T* in, size_t n, float* work, hipStream_t s) {
+    const size_t want = (n + 256 * 16 - 1) / (256 * 16);
+    const int nb = want < 1 ? 1 : (want < (size_t)kRangeBlocks ? (int)want : kRangeBlocks);
+    hipLaunchKernelGGL((k_absmax_partial<T>), dim3(nb), dim3(256), 0, s, in, n, work + 2);
     hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, (const float*)(work + 2), nb, work);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_range_scale(const float2* in, size_t n, float* work, hipStream_t s) {
+    return range_scale_t(in, n, work, s);
+}
+
+hipError_t launch_range_scale(const float* in, size_t n, float* work, hipStream_t s) {
+    return range_scale_t(in, n, work, s);
 }
 
 }  // namespace cwo

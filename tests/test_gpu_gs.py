@@ -9,6 +9,15 @@ oracle's field before the constraint (1e-5 of max|w| is the FP32 bound on w itse
 zeros of |u| can be amplified, so the long trajectory itself is not compared
 element-wise (parity of the 200-step trajectory is unpinned); its error curve is
 reported and checked to stay finite and below its start.
+
+FP16 / BF16 storage of the padded spectrum: each FP16 propagation meets the plain
+storage bound (relative L2 <= 3e-3), so the same element bound is used with 3e-3 in
+place of 1e-5, and E_k, a norm of |v| over ||a2||, may move by at most 3e-3 ||v|| / ||a2||
+(| ||x|| - ||y|| | <= ||x - y||). The step itself is held to relative L2 <= 3e-3. BF16
+keeps 8 significand bits to FP16's 11, so its rounding error is 8 times larger and its
+bounds are 8 times wider (2.4e-2): the constraint between the two propagations turns
+the phase of small |v| by e/|v| as the last one does, which at BF16's error size uses
+up the margin that the FP16 bound leaves.
 """
 import sys
 
@@ -37,13 +46,13 @@ def note(msg):
     sys.stdout.flush()
 
 
-def one_step_check(ctx, u_np, a1, a2, dx, lam, z, label):
+def one_step_check(ctx, u_np, a1, a2, dx, lam, z, label, precision="f32", eps=1e-5):
     import torch
     t = torch.from_numpy(u_np.astype(np.complex64)).cuda()
     ta1 = torch.from_numpy(a1.astype(np.float32)).cuda()
     ta2 = torch.from_numpy(a2.astype(np.float32)).cuda()
-    note("%s gs 1 step n=%s" % (label, u_np.shape))
-    err = ctx.gs(t, ta1, ta2, dx, dx, lam, z, iterations=1)
+    note("%s gs 1 step n=%s %s" % (label, u_np.shape, precision))
+    err = ctx.gs(t, ta1, ta2, dx, dx, lam, z, iterations=1, precision=precision)
     torch.cuda.synchronize()
     u1_ref, e0_ref = G.iteration(u_np.astype(np.complex64), a1, a2, dx, lam, z)
     # the same step written out, to get w (the field before the last constraint)
@@ -54,17 +63,21 @@ def one_step_check(ctx, u_np, a1, a2, dx, lam, z, label):
     rl = D.rel_l2(y, u1_ref)
     peak = float(np.max(np.abs(u1_ref)))
     aw = np.abs(w)
-    cond = np.minimum(2.0, 1e-5 * aw.max() / np.maximum(aw, 1e-300))
-    bound = 1e-5 * peak + a1.astype(np.float64) * cond
+    cond = np.minimum(2.0, eps * aw.max() / np.maximum(aw, 1e-300))
+    bound = eps * peak + a1.astype(np.float64) * cond
     diff = np.abs(y - u1_ref)
     worst = float(np.max(diff / bound))
     plain = float(np.max(diff)) / peak
     e0 = float(err.cpu().numpy()[0])
     note("%s rel_l2=%.3e max_abs_err/peak=%.3e worst/bound=%.3f E0 gpu=%.8f oracle=%.8f"
          % (label, rl, plain, worst, e0, e0_ref))
-    assert rl <= 1e-5
     assert worst <= 1.0
-    assert abs(e0 - e0_ref) <= 1e-5 * e0_ref
+    if precision == "f32":
+        assert rl <= 1e-5
+        assert abs(e0 - e0_ref) <= 1e-5 * e0_ref
+    else:
+        assert rl <= eps
+        assert abs(e0 - e0_ref) <= eps * np.linalg.norm(v) / np.linalg.norm(a2.astype(np.float64))
     return t
 
 
@@ -117,3 +130,43 @@ def test_gs_zero_iterations_and_validation(ctx):
     assert torch.equal(u, keep)
     with pytest.raises(cwo.CwoError):
         ctx.gs(u, a, a, 10e-6, 10e-6, 633e-9, float("nan"), iterations=1)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_gs_low_precision_storage(ctx, prec):
+    import torch
+    n = 256
+    a1 = W.rectangles_amplitude(n, 341, side_lo=8, side_hi=64)
+    a2 = W.rectangles_amplitude(n, 342, side_lo=8, side_hi=64)
+    u0 = (a1 * np.exp(1j * W.random_phase(n, 343))).astype(np.complex64)
+    eps = 3e-3 if prec == "f16" else 2.4e-2
+    one_step_check(ctx, u0, a1, a2, 8e-6, 532e-9, 0.02, "gs-256 k=0", prec, eps)
+    # the large workload: one step, then the error curve of 50 iterations against FP32
+    a1, a2, u0 = W.gs_problem(2048)
+    g = W.GS_2048
+    one_step_check(ctx, u0, a1, a2, g.pitch, g.wavelength, g.z, "gs-2048 k=0", prec, eps)
+    ta1 = torch.from_numpy(a1).cuda()
+    ta2 = torch.from_numpy(a2).cuda()
+    curves = {}
+    for p in ("f32", prec):
+        t = torch.from_numpy(u0).cuda()
+        curves[p] = ctx.gs(t, ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=50,
+                           precision=p).cpu().numpy().astype(np.float64)
+    d = np.abs(curves[prec] - curves["f32"])
+    note("gs-2048 %s E_0=%.5f E_49=%.5f (f32 %.5f %.5f) max|dE|=%.3e"
+         % (prec, curves[prec][0], curves[prec][-1], curves["f32"][0], curves["f32"][-1], d.max()))
+    assert np.all(np.isfinite(curves[prec])) and curves[prec][-1] < curves[prec][0]
+    assert d.max() <= 0.02 * curves["f32"][0]
+
+
+def test_gs_low_precision_rejects_nopad(ctx):
+    import torch
+    from paper_1107_5578_amd import cwo
+    u = torch.from_numpy(W.uniform_random_field(64, 3)).cuda()
+    a = torch.ones((64, 64), dtype=torch.float32, device="cuda")
+    import ctypes
+    p = cwo.make_params(64, 64, 10e-6, 10e-6, 633e-9, 0.1, cwo.ANGULAR, "f16", True)
+    st = ctx._lib.cwo_gs(ctx.handle, ctypes.byref(p), ctypes.c_void_p(a.data_ptr()),
+                         ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(u.data_ptr()), 1,
+                         None, None)
+    assert st == cwo.CWO_ERR_UNSUPPORTED
