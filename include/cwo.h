@@ -71,13 +71,21 @@ typedef enum {
  * complex64. FP16/BF16 store each complex as two 16-bit values (round to nearest even);
  * FP16 also scales the field by 2^-e (e = binary exponent of its largest component, found
  * on the device) and every transform by a power of two, undone exactly at the output.
- * Built for cwo_asm / cwo_fresnel (and single jobs of cwo_batch) in padded mode;
- * elsewhere CWO_ERR_UNSUPPORTED. */
+ * Built for cwo_asm / cwo_fresnel (and single jobs of cwo_batch) and cwo_gs in padded
+ * mode; elsewhere CWO_ERR_UNSUPPORTED. */
 typedef enum { CWO_PREC_F32 = 0, CWO_PREC_F16_STORAGE = 1, CWO_PREC_BF16_STORAGE = 2 } cwo_precision;
 
 /* Flags. CWO_FLAG_NOPAD keeps M = N (circular convolution without padding); it exists for
- * exactness checks such as the plane-wave eigenfunction test, not for production use. */
-enum { CWO_FLAG_NOPAD = 1u };
+ * exactness checks such as the plane-wave eigenfunction test, not for production use.
+ * CWO_FLAG_FRESNEL_TF (CWO_FRESNEL_CONV only, including z-stacks and batches) multiplies
+ * the spectrum by the Fourier transform of the continuous Fresnel kernel (Sec. 2.1.1),
+ *     H(fx, fy) = exp(i k z) exp(-i pi lambda z (fx^2 + fy^2)),
+ * at the padded grid's frequencies, instead of by C * DFT of the sampled impulse response
+ * (the paper's numerical form, the default). The two agree where the sampled chirp is
+ * itself band-limited by the grid; elsewhere they are different approximations. Phases
+ * are reduced modulo one revolution in FP64. Any other kind with this flag:
+ * CWO_ERR_INVALID. */
+enum { CWO_FLAG_NOPAD = 1u, CWO_FLAG_FRESNEL_TF = 2u };
 
 typedef struct {
     int32_t nx, ny;      /* field size, each a power of two in [16, 4096]; x is the fastest axis */

@@ -29,10 +29,11 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 struct FresnelKey {
     int mx, nx, my, ny;
     double dx, dy, lam, z;
-    bool unit;  // the shifted form's kernel factors: no constant, chirp pitches sqrt(p0 p1)
+    bool unit;      // the shifted form's kernel factors: no constant, chirp pitches sqrt(p0 p1)
+    bool analytic;  // the analytic transfer function instead of the DFT of the sampled chirps
     bool operator==(const FresnelKey& o) const {
         return mx == o.mx && nx == o.nx && my == o.my && ny == o.ny && dx == o.dx && dy == o.dy &&
-               lam == o.lam && z == o.z && unit == o.unit;
+               lam == o.lam && z == o.z && unit == o.unit && analytic == o.analytic;
     }
 };
 
@@ -243,7 +244,8 @@ cwo_status validate_geometry(const cwo_params* p, int kind, bool low_prec = fals
     if (kind != CWO_ANGULAR && kind != CWO_FRESNEL_CONV) return CWO_ERR_INVALID;
     if (p->kind != 0 && p->kind != kind) return CWO_ERR_INVALID;
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->wavelength)) return CWO_ERR_INVALID;
-    if ((p->flags & ~(uint32_t)CWO_FLAG_NOPAD) != 0) return CWO_ERR_INVALID;
+    const uint32_t allowed = CWO_FLAG_NOPAD | (kind == CWO_FRESNEL_CONV ? CWO_FLAG_FRESNEL_TF : 0u);
+    if ((p->flags & ~allowed) != 0) return CWO_ERR_INVALID;
     if (p->precision < CWO_PREC_F32 || p->precision > CWO_PREC_BF16_STORAGE) return CWO_ERR_INVALID;
     if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN ||
         p->ny > kMaxN)
@@ -302,6 +304,14 @@ void fresnel_constant(double dx, double dy, double lam, double z, double* re, do
     *im = -amp * std::cos(ang);
 }
 
+// exp(i k z), k z reduced in revolutions in FP64 (constant of the analytic transfer function)
+void phase_constant(double lam, double z, double* re, double* im) {
+    const double t = z / lam;
+    const double ang = 2.0 * M_PI * (t - std::nearbyint(t));
+    *re = std::cos(ang);
+    *im = std::sin(ang);
+}
+
 cwo::FresnelPlanes fresnel_planes(const cwo_params* p, const Geometry& g, const double* z, int nz) {
     cwo::FresnelPlanes fp;
     std::memset(&fp, 0, sizeof(fp));
@@ -312,9 +322,14 @@ cwo::FresnelPlanes fresnel_planes(const cwo_params* p, const Geometry& g, const 
     fp.dx = p->dx;
     fp.dy = p->dy;
     fp.nz = nz;
+    fp.analytic = (p->flags & CWO_FLAG_FRESNEL_TF) != 0;
     for (int k = 0; k < nz; ++k) {
         fp.inv2lz[k] = 0.5 / (p->wavelength * z[k]);
-        fresnel_constant(p->dx, p->dy, p->wavelength, z[k], &fp.cre[k], &fp.cim[k]);
+        fp.hlz[k] = 0.5 * p->wavelength * z[k];
+        if (fp.analytic)
+            phase_constant(p->wavelength, z[k], &fp.cre[k], &fp.cim[k]);
+        else
+            fresnel_constant(p->dx, p->dy, p->wavelength, z[k], &fp.cre[k], &fp.cim[k]);
     }
     return fp;
 }
@@ -359,9 +374,13 @@ const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hip
     fp.dy = key.dy;
     fp.nz = 1;
     fp.inv2lz[0] = 0.5 / (key.lam * key.z);
+    fp.hlz[0] = 0.5 * key.lam * key.z;
+    fp.analytic = key.analytic;
     if (key.unit) {
         fp.cre[0] = 1.0;
         fp.cim[0] = 0.0;
+    } else if (key.analytic) {
+        phase_constant(key.lam, key.z, &fp.cre[0], &fp.cim[0]);
     } else {
         fresnel_constant(key.dx, key.dy, key.lam, key.z, &fp.cre[0], &fp.cim[0]);
     }
@@ -377,7 +396,8 @@ const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hip
 
 const float2* fresnel_factors(cwo_ctx* c, Workspace& ws, const cwo_params* p, const Geometry& g,
                               hipStream_t s, cwo_status* st) {
-    const FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z, false};
+    const FresnelKey key{g.mx, g.nx, g.my, g.ny, p->dx, p->dy, p->wavelength, p->z, false,
+                         (p->flags & CWO_FLAG_FRESNEL_TF) != 0};
     return factor_table(c, ws, key, s, st);
 }
 
@@ -1018,7 +1038,7 @@ cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresn
     // the convolution kernel exp(i pi S d^2), S = p0 p1/(lambda z), is the Fresnel impulse
     // response of pitch sqrt(p0 p1); its factors carry no constant
     const FresnelKey key{g.mx, g.nx, g.my, g.ny, std::sqrt(p->dx * w->dx1),
-                         std::sqrt(p->dy * w->dy1), p->wavelength, p->z, true};
+                         std::sqrt(p->dy * w->dy1), p->wavelength, p->z, true, false};
     const float2* hfac = factor_table(c, ws, key, s, &st);
     if (!hfac) return st;
     cwo::SfPlan sp;

@@ -132,14 +132,21 @@ hipError_t launch_gs_errors(const double* num, const float* amp, double* den_wor
 // Fresnel transfer-function factors of up to kZChunk planes that share the geometry:
 // plane k gets Hx_k = C_k * DFT_mx(hx_k) at out + k*(mx+my) and Hy_k = DFT_my(hy_k) right
 // after it, where h*_k are the sampled 1-D chirps exp(i pi (s(d) pitch)^2 / (lambda z_k)).
+// With `analytic` set, the factors are instead the two halves of the Fourier transform of
+// the continuous Fresnel kernel: Hx_k = C_k exp(-i pi lambda z_k fx^2), Hy_k =
+// exp(-i pi lambda z_k fy^2) at the padded grid's frequencies.
 struct FresnelPlanes {
     int mx, nx, my, ny;
     double dx, dy;
     int nz;
+    int analytic;                 // 0: DFT of the sampled chirps, 1: analytic factors
     double inv2lz[kZChunk];       // 1 / (2 lambda z_k): chirp phase in revolutions per m^2
-    double cre[kZChunk], cim[kZChunk];  // C_k = dx dy exp(i k z_k) / (i lambda z_k)
+    double hlz[kZChunk];          // lambda z_k / 2: analytic phase in revolutions per (1/m)^2
+    double cre[kZChunk], cim[kZChunk];  // C_k: dx dy exp(i k z_k) / (i lambda z_k), or
+                                        // exp(i k z_k) for the analytic factors
 };
-// work must hold mx + my double2 (the FP64 twiddle tables); mx, my <= 8192.
+// work must hold mx + my double2 (the FP64 twiddle tables; unused by the analytic
+// factors); mx, my <= 8192.
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s);
 

@@ -66,11 +66,36 @@ __global__ __launch_bounds__(256) void k_chirp_fft(const double2* __restrict__ t
     }
 }
 
+// Analytic factors: one thread per entry (blockIdx.y = plane). Entry i < mx is Hx at
+// fx = s(i)/(mx dx), the rest Hy at fy = s(i - mx)/(my dy), with s(p) = p for p < m/2 and
+// p - m above; the phase -lambda z f^2 / 2 (revolutions) is reduced modulo one in FP64
+// before the sine and cosine, then Hx takes the plane constant.
+__global__ __launch_bounds__(256) void k_fresnel_tf(float2* __restrict__ out, FresnelPlanes fp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= fp.mx + fp.my) return;
+    const bool xa = i < fp.mx;
+    const int d = xa ? i : i - fp.mx, m = xa ? fp.mx : fp.my;
+    const double f = (double)(d < m / 2 ? d : d - m) / ((double)m * (xa ? fp.dx : fp.dy));
+    const double t = -fp.hlz[k] * (f * f);
+    const double r = t - rint(t);
+    double sn, cs;
+    sincospi(2.0 * r, &sn, &cs);
+    const double cr = xa ? fp.cre[k] : 1.0, ci = xa ? fp.cim[k] : 0.0;
+    out[(size_t)k * (fp.mx + fp.my) + i] =
+        make_float2((float)(cs * cr - sn * ci), (float)(cs * ci + sn * cr));
+}
+
 // ---- host launchers ------------------------------------------------------------
 
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s) {
     if (fp.mx > kChirpMaxM || fp.my > kChirpMaxM) return hipErrorInvalidValue;
+    if (fp.analytic) {
+        hipLaunchKernelGGL(k_fresnel_tf, dim3((fp.mx + fp.my + 255) / 256, fp.nz), dim3(256), 0, s,
+                           out, fp);
+        return hipGetLastError();
+    }
     const int len = fp.mx + fp.my;
     double2* tw64 = work;
     hipLaunchKernelGGL(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);

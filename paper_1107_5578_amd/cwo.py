@@ -37,6 +37,7 @@ _PRECISIONS = {"f32": PREC_F32, "fp32": PREC_F32, "f16": PREC_F16, "fp16": PREC_
                "bf16": PREC_BF16}
 
 FLAG_NOPAD = 1
+FLAG_FRESNEL_TF = 2  # Fresnel: analytic transfer function instead of the sampled kernel
 
 STAGE_ROW_FWD = 0
 STAGE_COL = 1
@@ -182,11 +183,11 @@ def strerror(status: int) -> str:
 
 
 def make_params(nx, ny, dx, dy=None, wavelength=633e-9, z=0.1, kind=0, precision="f32",
-                nopad=False) -> Params:
+                nopad=False, fresnel_tf=False) -> Params:
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return Params(int(nx), int(ny), float(dx), float(dx if dy is None else dy),
                   float(wavelength), float(z), int(kind), prec,
-                  FLAG_NOPAD if nopad else 0)
+                  (FLAG_NOPAD if nopad else 0) | (FLAG_FRESNEL_TF if fresnel_tf else 0))
 
 
 def check_params(p: Params, kind: int) -> int:
@@ -252,11 +253,12 @@ class Context:
             stream = torch.cuda.current_stream(u.device)
         return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
-    def _propagate(self, fn, kind, u, dx, dy, wavelength, z, precision, nopad, out, stream):
+    def _propagate(self, fn, kind, u, dx, dy, wavelength, z, precision, nopad, out, stream,
+                   fresnel_tf=False):
         import torch
         u = self._field(u)
         ny, nx = u.shape
-        p = make_params(nx, ny, dx, dy, wavelength, z, kind, precision, nopad)
+        p = make_params(nx, ny, dx, dy, wavelength, z, kind, precision, nopad, fresnel_tf)
         if out is None:
             out = torch.empty_like(u)
         else:
@@ -276,10 +278,11 @@ class Context:
                                nopad, out, stream)
 
     def fresnel(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
-                nopad=False, out=None, stream=None):
-        """Fresnel diffraction (convolution form) by z."""
+                nopad=False, out=None, stream=None, fresnel_tf=False):
+        """Fresnel diffraction (convolution form) by z; fresnel_tf takes the analytic
+        transfer function instead of the transformed sampled kernel."""
         return self._propagate(self._lib.cwo_fresnel, FRESNEL_CONV, u, dx, dy, wavelength, z,
-                               precision, nopad, out, stream)
+                               precision, nopad, out, stream, fresnel_tf)
 
     def fresnel_fourier(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, out=None,
                         stream=None):
@@ -398,14 +401,14 @@ class Context:
         return t.row_form, t.zchunk, t.us_per_plane
 
     def zstack(self, u, z, dx=10e-6, dy=None, wavelength=633e-9, kind="asm", precision="f32",
-               nopad=False, out=None, stream=None):
+               nopad=False, out=None, stream=None, fresnel_tf=False):
         """Propagate one field to every distance in z; returns [nz, ny, nx] planes."""
         import torch
         u = self._field(u)
         ny, nx = u.shape
         zs = [float(v) for v in z]
         k = KINDS[kind] if isinstance(kind, str) else int(kind)
-        p = make_params(nx, ny, dx, dy, wavelength, 0.0, k, precision, nopad)
+        p = make_params(nx, ny, dx, dy, wavelength, 0.0, k, precision, nopad, fresnel_tf)
         if out is None:
             out = torch.empty((len(zs), ny, nx), dtype=torch.complex64, device=u.device)
         elif (out.dtype != torch.complex64 or tuple(out.shape) != (len(zs), ny, nx)
@@ -500,7 +503,8 @@ class Context:
             k = KINDS[kind] if isinstance(kind, str) else int(kind)
             arr[i].p = make_params(nx, ny, kw.get("dx", 10e-6), kw.get("dy"),
                                    kw.get("wavelength", 633e-9), kw.get("z", 0.1), k,
-                                   kw.get("precision", "f32"), kw.get("nopad", False))
+                                   kw.get("precision", "f32"), kw.get("nopad", False),
+                                   kw.get("fresnel_tf", False))
             arr[i].inp = u.data_ptr()
             arr[i].out = out.data_ptr()
         st = self._lib.cwo_batch(self.handle, arr, len(jobs), self._stream(first, stream))

@@ -84,6 +84,18 @@ def test_kind_flags_precision_checks():
     assert cwo.load().cwo_check_params(None, cwo.ANGULAR) == cwo.CWO_ERR_INVALID
 
 
+def test_fresnel_tf_flag_only_for_the_convolution_form():
+    for nopad in (False, True):
+        p = cwo.make_params(64, 32, 10e-6, 8e-6, 633e-9, -0.1, cwo.FRESNEL_CONV, "f32", nopad, True)
+        assert p.flags == (cwo.FLAG_FRESNEL_TF | (cwo.FLAG_NOPAD if nopad else 0))
+        assert cwo.check_params(p, cwo.FRESNEL_CONV) == cwo.CWO_OK
+    p = cwo.make_params(64, 64, 10e-6, None, 633e-9, 0.1, cwo.FRESNEL_CONV, "f16", False, True)
+    assert cwo.check_params(p, cwo.FRESNEL_CONV) == cwo.CWO_OK
+    for kind in (cwo.ANGULAR, cwo.FRESNEL_FOURIER, cwo.FRESNEL_SHIFTED):
+        p = cwo.make_params(64, 64, 10e-6, None, 633e-9, 0.1, kind, "f32", False, True)
+        assert cwo.check_params(p, kind) == cwo.CWO_ERR_INVALID
+
+
 def test_scratch_bytes():
     lib = cwo.load()
     p = cwo.make_params(2048, 2048, 8e-6, z=0.5)
