@@ -171,6 +171,32 @@ def other_forms(ctx, torch, W, u, u_np, cfg, stream, with_oracle):
 
     ms = time_call(torch, stream, epi, 100, 5)
     rec("intensity_scale_u8", ms, 21 * n * n)
+
+    # point-light-source hologram (direct sum, arithmetic-bound): the paper's hologram
+    # geometry and point counts, synthetic point clouds
+    pc = W.PLS_2048
+    pls = {"workload": "%dx%d hologram, %g um pitch, %g nm, object offset (%g, %g, %g) m, "
+                       "synthetic points in a +-4 mm cube" % (pc.n, pc.n, pc.pitch * 1e6,
+                                                             pc.wavelength * 1e9, pc.ox, pc.oy,
+                                                             pc.oz)}
+    for count in pc.counts:
+        pts_np = W.pls_points(count, 7)
+        pts = torch.from_numpy(pts_np).to(u.device)
+        h = torch.empty((pc.n, pc.n), dtype=torch.float32, device=u.device)
+        ms = time_call(torch, stream, lambda: ctx.pls_cgh(pts, pc.n, pc.n, pc.pitch, pc.pitch,
+                                                          pc.wavelength, pc.ox, pc.oy, pc.oz,
+                                                          out=h), 3 if count > 5000 else 10, 1)
+        terms = count * pc.n * pc.n
+        e = {"ms": round(ms, 3), "terms_per_s": float("%.4g" % (terms / (ms * 1e-3)))}
+        if with_oracle:
+            from oracle import pls as PL
+            rows = [0, pc.n // 2]
+            ref = PL.cgh(pts_np, pc.n, pc.n, pc.pitch, pc.pitch, pc.wavelength, pc.ox, pc.oy,
+                         pc.oz, rows=rows)
+            e["rel_l2_vs_oracle_rows"] = float("%.3e" % rel_l2(h.cpu().numpy()[rows], ref))
+        pls[str(count)] = e
+        del pts, h
+    res["pls_cgh"] = pls
     return res
 
 

@@ -258,6 +258,37 @@ cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip
 cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* hip_stream);
 
+/* ---- point light sources (Sec. 2.4, Eqs. pls_fre and pls_fre_cgh) ----------------------
+ * A 3-D object as N point sources: point j has object coordinates (X_j, Y_j, Z_j) [m] and
+ * amplitude A_j, and sits at (ox + X_j, oy + Y_j, oz + Z_j) relative to the hologram's
+ * centre; hologram pixel (m, n) is at ((m - nx/2) px, (n - ny/2) py). With
+ * r_j^2 = (x - x_j)^2 + (y - y_j)^2 and z_j = oz + Z_j,
+ *     cwo_pls_cgh:   I(x, y) = sum_j A_j cos(pi r_j^2/(lambda z_j))            (float out)
+ *     cwo_pls_field: u(x, y) = exp(i k oz)/(i lambda oz)
+ *                              * sum_j A_j exp(+i pi r_j^2/(lambda z_j))       (complex64 out)
+ * (the printed exponent lacks the imaginary unit; the Fresnel wavelet is meant, and the
+ * prefactor takes the object's reference distance oz, as the paper's listing sets it).
+ * points: device float [npoints][4] records (X, Y, Z, A), 16-byte aligned, read only;
+ * npoints == 0 writes zeros. out: device [ny][nx], float (hologram) or complex64 (field),
+ * caller-owned. Each term's phase is evaluated and reduced modulo one revolution in FP64,
+ * its cosine/sine in FP32; partial sums over 512 points are FP32, the total FP64. Points
+ * with z_j == 0 give non-finite values (not checked on the device). Sizes: 1..16384 per
+ * axis, any value. Errors, checked in this order: p null -> CWO_ERR_INVALID; sizes out of
+ * range -> CWO_ERR_UNSUPPORTED; null pointers, misaligned points, npoints < 0, non-finite
+ * or non-positive pitch/wavelength, non-finite offsets or oz == 0 -> CWO_ERR_INVALID.
+ * Scratch: 32 bytes per point. Stream-ordered. */
+typedef struct {
+    int32_t nx, ny;        /* hologram pixels */
+    double px, py;         /* hologram pitch [m] */
+    double wavelength;     /* [m] */
+    double ox, oy, oz;     /* object offset [m]; oz is the reference distance, != 0 */
+} cwo_pls_params;
+
+cwo_status cwo_pls_cgh(cwo_ctx* ctx, const cwo_pls_params* p, const float* points,
+                       int32_t npoints, float* out, void* hip_stream);
+cwo_status cwo_pls_field(cwo_ctx* ctx, const cwo_pls_params* p, const float* points,
+                         int32_t npoints, void* out, void* hip_stream);
+
 /* ---- serving (continuous batching) ----------------------------------------------------
  * cwo_submit queues one job and returns at once with a ticket; a scheduler thread of the
  * context admits queued jobs in arrival order when one of its 4 slots (each with its own
@@ -301,6 +332,7 @@ typedef enum {
     CWO_STAGE_TABLES = 3,    /* Fresnel transfer-vector generation */
     CWO_STAGE_COL_Z = 4,     /* z-stack column pass: one forward FFT, per plane H x IFFT */
     CWO_STAGE_ROW_GS = 5,    /* ping-pong row pass: IFFT, crop, constraint, pad, FFT */
+    CWO_STAGE_PLS = 6,       /* point-light-source direct sum (with its point pre-pass) */
     CWO_STAGE_COUNT = 8
 } cwo_stage;
 

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcwo.so")
 SOURCES = ["plane.hip", "shifted.hip", "fourier.hip", "sfresnel.hip", "zstack.hip", "gs.hip",
-           "tables.hip", "epilogue.hip", "cwo.cpp"]
+           "tables.hip", "epilogue.hip", "pls.hip", "cwo.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay disabled: the compiler must emit scalar FP32 math.

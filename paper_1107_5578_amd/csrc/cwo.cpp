@@ -60,14 +60,15 @@ struct Workspace {
     Buffer rwork;                     // range pre-pass of FP16 storage (scale, partials)
     Buffer fourier;                   // chirp tables of the Fresnel Fourier and shifted forms
     Buffer ework;                     // min/max partials of the scale epilogue
+    Buffer pls;                       // FP64 point records of the point-light-source sums
     std::list<FresnelEntry> fresnel;  // most recently used first
     size_t budget = 0;                // 0: unbounded (serving slots are bounded by admission)
     size_t held() const {
         return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes +
-               fourier.bytes + ework.bytes;
+               fourier.bytes + ework.bytes + pls.bytes;
     }
     void release() {
-        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier, &ework}) {
+        for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier, &ework, &pls}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->bytes = 0;
@@ -1067,6 +1068,71 @@ cwo_status cwo_fresnel_shifted(cwo_ctx* c, const cwo_params* p, const cwo_sfresn
                 return cwo::launch_sf_row_inv(buf, (float2*)out, g.nx, g.ny, scale, tabs, twx, s);
             }));
     return CWO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Point-light-source sums: sizes 1..kPlsMaxN per axis (any, not only powers of two),
+// finite positive pitches and wavelength, finite offsets, oz != 0.
+constexpr int kPlsMaxN = 16384;
+
+cwo_status validate_pls(const cwo_pls_params* p, const float* points, int32_t npoints,
+                        const void* out) {
+    if (!p) return CWO_ERR_INVALID;
+    if (p->nx < 1 || p->ny < 1 || p->nx > kPlsMaxN || p->ny > kPlsMaxN) return CWO_ERR_UNSUPPORTED;
+    if (!out || npoints < 0 || (npoints > 0 && !points)) return CWO_ERR_INVALID;
+    if (points && (reinterpret_cast<uintptr_t>(points) & 15) != 0) return CWO_ERR_INVALID;
+    if (!finite_pos(p->px) || !finite_pos(p->py) || !finite_pos(p->wavelength))
+        return CWO_ERR_INVALID;
+    if (!std::isfinite(p->ox) || !std::isfinite(p->oy) || !std::isfinite(p->oz) || p->oz == 0.0)
+        return CWO_ERR_INVALID;
+    return CWO_OK;
+}
+
+cwo_status pls_run(cwo_ctx* c, const cwo_pls_params* p, const float* points, int32_t npoints,
+                   void* out, bool field, hipStream_t s) {
+    if (!c) return CWO_ERR_INVALID;
+    cwo_status st = validate_pls(p, points, npoints, out);
+    if (st != CWO_OK) return st;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if ((st = begin(c)) != CWO_OK) return st;
+    void* work = ensure(c, c->ws, c->ws.pls, cwo::pls_work_bytes(npoints), &st);
+    if (!work) return st;
+    cwo::PlsParams pp;
+    pp.nx = p->nx;
+    pp.ny = p->ny;
+    pp.px = p->px;
+    pp.py = p->py;
+    pp.lam = p->wavelength;
+    pp.ox = p->ox;
+    pp.oy = p->oy;
+    pp.oz = p->oz;
+    // exp(i k oz)/(i lambda oz), k oz reduced in revolutions in FP64
+    const double t = p->oz / p->wavelength;
+    const double ang = 2.0 * M_PI * (t - std::nearbyint(t));
+    const double inv = 1.0 / (p->wavelength * p->oz);
+    pp.cre = std::sin(ang) * inv;  // (cos + i sin)/i = sin - i cos
+    pp.cim = -std::cos(ang) * inv;
+    CWO_HIP(c, timed(c, CWO_STAGE_PLS, s, [&] {
+                return cwo::launch_pls(points, npoints, work, out, field, pp, s);
+            }));
+    return CWO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cwo_status cwo_pls_cgh(cwo_ctx* c, const cwo_pls_params* p, const float* points, int32_t npoints,
+                       float* out, void* stream) {
+    return pls_run(c, p, points, npoints, out, false, (hipStream_t)stream);
+}
+
+cwo_status cwo_pls_field(cwo_ctx* c, const cwo_pls_params* p, const float* points,
+                         int32_t npoints, void* out, void* stream) {
+    return pls_run(c, p, points, npoints, out, true, (hipStream_t)stream);
 }
 
 cwo_status cwo_intensity(cwo_ctx* c, const void* in, void* out, size_t n, void* stream) {

@@ -150,6 +150,20 @@ struct FresnelPlanes {
 hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes& fp,
                                  hipStream_t s);
 
+// Point-light-source sums (hologram or field) over npts points given as float
+// (X, Y, Z, A) records (16-byte aligned); work holds pls_work_bytes(npts). The hologram
+// pixel (m, n) sits at ((m - nx/2) px, (n - ny/2) py); point j at (ox + X, oy + Y,
+// oz + Z). The field is multiplied by (cre, cim).
+struct PlsParams {
+    int nx, ny;
+    double px, py, lam;
+    double ox, oy, oz;
+    double cre, cim;
+};
+hipError_t launch_pls(const float* points, int npts, void* work, void* out, bool field,
+                      const PlsParams& pp, hipStream_t s);
+size_t pls_work_bytes(int npts);
+
 // Independent fields of one geometry in one launch per pass: the row forward pass reads
 // plane k from ins.in[k] into scratch plane k, the row inverse writes plane k to
 // outs.out[k] (batch <= kZChunk; complex64).

@@ -91,6 +91,14 @@ class Shift(ctypes.Structure):
                 ("cy", ctypes.c_double), ("wy", ctypes.c_double)]
 
 
+class PlsParams(ctypes.Structure):
+    """cwo_pls_params: hologram size and pitch, wavelength, object offset [m]."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("px", ctypes.c_double), ("py", ctypes.c_double),
+                ("wavelength", ctypes.c_double),
+                ("ox", ctypes.c_double), ("oy", ctypes.c_double), ("oz", ctypes.c_double)]
+
+
 class SFresnel(ctypes.Structure):
     """cwo_sfresnel: destination pitch and the two window centres [m]."""
     _fields_ = [("dx1", ctypes.c_double), ("dy1", ctypes.c_double),
@@ -120,6 +128,11 @@ SIGNATURES = {
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_intensity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "cwo_pls_cgh": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PlsParams), ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_pls_field": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PlsParams),
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "cwo_phase": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]),
     "cwo_polar": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -366,6 +379,42 @@ class Context:
         call.__name__ = "cwo_fresnel_shifted"
         return self._propagate(call, FRESNEL_SHIFTED, u, dx0, dy0, wavelength, z, "f32", False,
                                out, stream)
+
+    def _pls(self, fn, points, nx, ny, px, py, wavelength, ox, oy, oz, out, stream, field):
+        import torch
+        if (not isinstance(points, torch.Tensor) or points.dtype != torch.float32
+                or points.dim() != 2 or points.shape[1] != 4 or not points.is_contiguous()
+                or points.device.type != "cuda"):
+            raise ValueError("points must be a contiguous float32 [N, 4] CUDA tensor (X, Y, Z, A)")
+        py = px if py is None else py
+        dtype = torch.complex64 if field else torch.float32
+        if out is None:
+            out = torch.empty((int(ny), int(nx)), dtype=dtype, device=points.device)
+        elif (out.dtype != dtype or tuple(out.shape) != (int(ny), int(nx))
+              or not out.is_contiguous() or out.device != points.device):
+            raise ValueError("out must be a contiguous [ny, nx] tensor of the right dtype")
+        p = PlsParams(int(nx), int(ny), float(px), float(py), float(wavelength), float(ox),
+                      float(oy), float(oz))
+        st = fn(self.handle, ctypes.byref(p), ctypes.c_void_p(points.data_ptr()),
+                int(points.shape[0]), ctypes.c_void_p(out.data_ptr()),
+                self._stream(points, stream))
+        if st != CWO_OK:
+            raise CwoError(st, fn.__name__)
+        return out
+
+    def pls_cgh(self, points, nx, ny, px=10e-6, py=None, wavelength=633e-9, ox=0.0, oy=0.0,
+                oz=0.1, out=None, stream=None):
+        """Point-light-source hologram I = sum_j A_j cos(pi r_j^2/(lambda z_j)), float
+        [ny, nx]; points: float32 [N, 4] (X, Y, Z, A) relative to the offset (ox, oy, oz)."""
+        return self._pls(self._lib.cwo_pls_cgh, points, nx, ny, px, py, wavelength, ox, oy, oz,
+                         out, stream, False)
+
+    def pls_field(self, points, nx, ny, px=10e-6, py=None, wavelength=633e-9, ox=0.0, oy=0.0,
+                  oz=0.1, out=None, stream=None):
+        """Point-light-source complex field exp(i k oz)/(i lambda oz) sum_j A_j
+        exp(i pi r_j^2/(lambda z_j)), complex64 [ny, nx]."""
+        return self._pls(self._lib.cwo_pls_field, points, nx, ny, px, py, wavelength, ox, oy,
+                         oz, out, stream, True)
 
     def asm_shifted(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, ox=0.0, oy=0.0,
                     cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None):

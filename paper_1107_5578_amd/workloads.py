@@ -128,6 +128,35 @@ def gs_problem(n: int = 2048, seeds=(41, 42, 43)):
     return a1, a2, u0
 
 
+# ---- point-light-source object ----------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class PlsConfig:
+    """A hologram of n x n pixels of pitch `pitch` from a point object offset by
+    (ox, oy, oz); point counts as in the paper's hologram timings."""
+    n: int = 2048
+    pitch: float = 4e-6
+    wavelength: float = 633e-9
+    ox: float = 2500 * 4e-6
+    oy: float = -512 * 4e-6
+    oz: float = 0.2
+    counts: tuple = (248, 4596, 11646)
+
+
+PLS_2048 = PlsConfig()
+
+
+def pls_points(count: int, seed: int, half_extent: float = 4e-3) -> np.ndarray:
+    """Synthetic stand-in for a scanned 3-D object: `count` points uniform in a cube of
+    half-width `half_extent` (the object's coordinates normalised to +-4 mm, as the paper
+    scales its model), amplitudes uniform on [0.5, 1]; float32 [count][4] (X, Y, Z, A)."""
+    rng = np.random.default_rng(seed)
+    pts = np.empty((count, 4), dtype=np.float32)
+    pts[:, :3] = rng.uniform(-half_extent, half_extent, (count, 3))
+    pts[:, 3] = rng.uniform(0.5, 1.0, count)
+    return pts
+
+
 # ---- serving request stream --------------------------------------------------
 
 @dataclasses.dataclass(frozen=True)
