@@ -172,6 +172,17 @@ def other_forms(ctx, torch, W, u, u_np, cfg, stream, with_oracle):
     ms = time_call(torch, stream, epi, 100, 5)
     rec("intensity_scale_u8", ms, 21 * n * n)
 
+    # intensity fused into the last pass vs a propagation followed by the epilogue
+    inten = torch.empty((n, n), dtype=torch.float32, device=u.device)
+    ms_f = time_call(torch, stream, lambda: ctx.asm_intensity(u, cfg.pitch, cfg.pitch,
+                                                              cfg.wavelength, cfg.z, out=inten),
+                     100, 5)
+    ms_s = time_call(torch, stream, lambda: ctx.intensity(ctx.asm(u, cfg.pitch, cfg.pitch,
+                                                                  cfg.wavelength, cfg.z, out=out)),
+                     100, 5)
+    rec("asm_intensity_fused", ms_f, 76 * n * n,
+        {"separate_ms": round(ms_s, 4), "fused_vs_separate": round(ms_s / ms_f, 3)})
+
     # point-light-source hologram (direct sum, arithmetic-bound): the paper's hologram
     # geometry and point counts, synthetic point clouds
     pc = W.PLS_2048

@@ -160,6 +160,17 @@ typedef struct {
 cwo_status cwo_fresnel_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_sfresnel* window,
                                const void* in, void* out, void* hip_stream);
 
+/* A propagation whose last pass stores the intensity |u|^2 of the result instead of u
+ * (the intensity epilogue of Sec. 3.1 fused into the row inverse store): out is device
+ * float [ny][nx], caller-owned, and equals cwo_intensity applied to the output of
+ * cwo_asm / cwo_fresnel with the same parameters, bit for bit, without writing or reading
+ * the complex result. Parameters, validation, precision and scratch as cwo_asm /
+ * cwo_fresnel; out may overlap in (the first pass has consumed in when out is written). */
+cwo_status cwo_asm_intensity(cwo_ctx* ctx, const cwo_params* p, const void* in, float* out,
+                             void* hip_stream);
+cwo_status cwo_fresnel_intensity(cwo_ctx* ctx, const cwo_params* p, const void* in, float* out,
+                                 void* hip_stream);
+
 /* Field epilogues of the paper's examples, n elements each, device pointers, ordered on
  * the stream; n == 0 does nothing, a null pointer with n > 0 is CWO_ERR_INVALID.
  *   cwo_intensity: out_f32[i] = re*re + im*im of in_c64[i] (Sec. 3.1), FP32, the two

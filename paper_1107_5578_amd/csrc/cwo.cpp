@@ -425,9 +425,11 @@ cwo_status begin(cwo_ctx* c) {
     return CWO_OK;
 }
 
+// intensity: out is float [ny][nx] and receives |u|^2 of the result (stored by the row
+// inverse pass instead of u).
 cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kind,
                             const void* in, void* out, hipStream_t s,
-                            const cwo::AsmShift* shift = nullptr) {
+                            const cwo::AsmShift* shift = nullptr, bool intensity = false) {
     cwo_status st = CWO_OK;
     const Geometry g = geometry(p);
     const float2* twx = twiddle_table(c, g.mx, s, &st);
@@ -486,13 +488,17 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
                 }));
     }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
+                if (intensity)
+                    return cwo::launch_row_inv_intensity(buf, (float*)out, g.nx, g.ny, g.mx, sto,
+                                                         twx, s);
                 return cwo::launch_row_inv(buf, fout, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s);
             }));
     return CWO_OK;
 }
 
 cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, void* out,
-                     void* stream, const cwo::AsmShift* shift = nullptr) {
+                     void* stream, const cwo::AsmShift* shift = nullptr,
+                     bool intensity = false) {
     if (!c) return CWO_ERR_INVALID;
     cwo_status st = validate(p, kind, true);
     if (st != CWO_OK) return st;
@@ -500,7 +506,7 @@ cwo_status propagate(cwo_ctx* c, const cwo_params* p, int kind, const void* in, 
     std::lock_guard<std::mutex> lock(c->mu);
     st = begin(c);
     if (st != CWO_OK) return st;
-    return propagate_locked(c, c->ws, p, kind, in, out, (hipStream_t)stream, shift);
+    return propagate_locked(c, c->ws, p, kind, in, out, (hipStream_t)stream, shift, intensity);
 }
 
 // One field to nz distances; plane k goes to outs[k]. The row transform of the field
@@ -971,6 +977,16 @@ cwo_status cwo_asm(cwo_ctx* c, const cwo_params* p, const void* in, void* out, v
 
 cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* out, void* stream) {
     return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream);
+}
+
+cwo_status cwo_asm_intensity(cwo_ctx* c, const cwo_params* p, const void* in, float* out,
+                             void* stream) {
+    return propagate(c, p, CWO_ANGULAR, in, out, stream, nullptr, true);
+}
+
+cwo_status cwo_fresnel_intensity(cwo_ctx* c, const cwo_params* p, const void* in, float* out,
+                                 void* stream) {
+    return propagate(c, p, CWO_FRESNEL_CONV, in, out, stream, nullptr, true);
 }
 
 cwo_status cwo_fresnel_fourier(cwo_ctx* c, const cwo_params* p, const void* in, void* out,

@@ -76,6 +76,9 @@ hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size
 hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,
                           size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
                           hipStream_t s);
+// The same for one plane, storing the intensity |u|^2 (float [ny][nx]) instead of u.
+hipError_t launch_row_inv_intensity(const void* in, float* out, int nx, int ny, int mx,
+                                    const Storage& st, const float2* tw, hipStream_t s);
 
 // in: batch planes of [ny][nx] (plane stride in_plane elements); out: [ny][mx] per plane
 hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx, int batch,
@@ -179,14 +182,26 @@ struct InTable {
     __device__ __forceinline__ const float2* operator()(int k) const { return in[k]; }
 };
 
+// Output of the row inverse passes: put(k, i, v) stores value v of element i (row-major
+// [ny][nx] index) of plane k.
 struct OutStrided {
     float2* out;
     size_t plane;
-    __device__ __forceinline__ float2* operator()(int k) const { return out + k * plane; }
+    __device__ __forceinline__ void put(int k, size_t i, float2 v) const { out[k * plane + i] = v; }
 };
 struct OutTable {
     float2* out[kZChunk];
-    __device__ __forceinline__ float2* operator()(int k) const { return out[k]; }
+    __device__ __forceinline__ void put(int k, size_t i, float2 v) const { out[k][i] = v; }
+};
+// The intensity |v|^2 instead of the field (Sec. 3.1), each product and the sum rounded
+// on its own in FP32 (no fused multiply-add), so it equals the intensity of the stored field.
+struct OutIntensity {
+    float* out;
+    size_t plane;
+    __device__ __forceinline__ void put(int k, size_t i, float2 v) const {
+#pragma clang fp contract(off)
+        out[k * plane + i] = v.x * v.x + v.y * v.y;
+    }
 };
 hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
                               size_t out_plane, const float2* tw, hipStream_t s);

@@ -150,15 +150,15 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv(
     for (int r = 0; r < E; ++r) v[0][r] = valid ? ST::dec(src[j + r * T]) : make_float2(0.f, 0.f);
     fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
-        float2* dst = outs(blockIdx.y) + (size_t)row * nx;
+        const size_t base = (size_t)row * nx;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int x = j + r * T;
             const float2 o = make_float2(v[0][r].x * scale, v[0][r].y * scale);
             if constexpr (HALF) {
-                if (r < E / 2) dst[x] = o;
+                if (r < E / 2) outs.put(blockIdx.y, base + x, o);
             } else {
-                if (x < nx) dst[x] = o;
+                if (x < nx) outs.put(blockIdx.y, base + x, o);
             }
         }
     }
@@ -200,12 +200,12 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv_pf(
         const int w = g * C::RPB + sub;
         if (w < rows) {
             const int pl = w / ny, row = w - pl * ny;
-            float2* dst = outs(pl) + (size_t)row * nx;
+            const size_t base = (size_t)row * nx;
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const int x = j + r * T;
                 if (HALF ? (r < E / 2) : (x < nx))
-                    dst[x] = make_float2(v[0][r].x * scale, v[0][r].y * scale);
+                    outs.put(pl, base + x, make_float2(v[0][r].x * scale, v[0][r].y * scale));
             }
         }
 #pragma unroll
@@ -409,6 +409,23 @@ hipError_t launch_row_inv_tab(const float2* in, const OutTable& outs, int nx, in
                               int batch, size_t in_plane, float scale, const float2* tw,
                               hipStream_t s) {
     return launch_row_inv_impl(in, outs, nx, ny, mx, batch, in_plane, scale, tw, s);
+}
+
+hipError_t launch_row_inv_intensity(const void* in, float* out, int nx, int ny, int mx,
+                                    const Storage& st, const float2* tw, hipStream_t s) {
+    const OutIntensity o{out, 0};
+    switch (st.prec) {
+        case 0:
+            return launch_row_inv_t<OutIntensity, StF32>(in, o, nx, ny, mx, 1, 0, st.out_scale,
+                                                         st.dyn_inv, tw, s, st.row_form);
+        case 1:
+            return launch_row_inv_t<OutIntensity, StF16>(in, o, nx, ny, mx, 1, 0, st.out_scale,
+                                                         st.dyn_inv, tw, s, st.row_form);
+        case 2:
+            return launch_row_inv_t<OutIntensity, StBF16>(in, o, nx, ny, mx, 1, 0, st.out_scale,
+                                                          st.dyn_inv, tw, s, st.row_form);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,

@@ -212,12 +212,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
         if (active) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                float2* dst = outs(pl) + (size_t)(y0 + p) * nx;
+                const size_t base = (size_t)(y0 + p) * nx;
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     const int x = j + r * T;
                     if (HALF ? (r < E / 2) : (x < nx))
-                        dst[x] = make_float2(v[p][r].x * scale, v[p][r].y * scale);
+                        outs.put(pl, base + x, make_float2(v[p][r].x * scale, v[p][r].y * scale));
                 }
             }
         }

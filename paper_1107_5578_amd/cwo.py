@@ -128,6 +128,11 @@ SIGNATURES = {
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_intensity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "cwo_asm_intensity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_fresnel_intensity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                               ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "cwo_pls_cgh": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PlsParams), ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_pls_field": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PlsParams),
@@ -379,6 +384,36 @@ class Context:
         call.__name__ = "cwo_fresnel_shifted"
         return self._propagate(call, FRESNEL_SHIFTED, u, dx0, dy0, wavelength, z, "f32", False,
                                out, stream)
+
+    def _propagate_intensity(self, fn, kind, u, dx, dy, wavelength, z, precision, nopad, out,
+                             stream, fresnel_tf=False):
+        import torch
+        u = self._field(u)
+        ny, nx = u.shape
+        p = make_params(nx, ny, dx, dy, wavelength, z, kind, precision, nopad, fresnel_tf)
+        if out is None:
+            out = torch.empty((ny, nx), dtype=torch.float32, device=u.device)
+        elif (out.dtype != torch.float32 or tuple(out.shape) != (ny, nx)
+              or not out.is_contiguous() or out.device != u.device):
+            raise ValueError("out must be a contiguous float32 [ny, nx] tensor on the field's device")
+        st = fn(self.handle, ctypes.byref(p), ctypes.c_void_p(u.data_ptr()),
+                ctypes.c_void_p(out.data_ptr()), self._stream(u, stream))
+        if st != CWO_OK:
+            raise CwoError(st, fn.__name__)
+        return out
+
+    def asm_intensity(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
+                      nopad=False, out=None, stream=None):
+        """|ASM propagation of u|^2, the intensity stored by the last pass (float [ny, nx])."""
+        return self._propagate_intensity(self._lib.cwo_asm_intensity, ANGULAR, u, dx, dy,
+                                         wavelength, z, precision, nopad, out, stream)
+
+    def fresnel_intensity(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
+                          nopad=False, out=None, stream=None, fresnel_tf=False):
+        """|Fresnel propagation of u|^2, the intensity stored by the last pass."""
+        return self._propagate_intensity(self._lib.cwo_fresnel_intensity, FRESNEL_CONV, u, dx,
+                                         dy, wavelength, z, precision, nopad, out, stream,
+                                         fresnel_tf)
 
     def _pls(self, fn, points, nx, ny, px, py, wavelength, ox, oy, oz, out, stream, field):
         import torch

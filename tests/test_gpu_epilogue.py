@@ -112,3 +112,31 @@ def test_kinoform_example(ctx):
     # the phase of a near-zero sample is ill-conditioned: bound the bulk, not the maximum
     assert dk.mean() <= 1e-5 and np.quantile(dk, 0.999) <= 1e-4
     assert diff.max() <= 2 and np.mean(diff > 0) <= 1e-3
+
+
+@pytest.mark.parametrize("kind,n,prec,nopad", [
+    ("asm", 256, "f32", False), ("fresnel", 128, "f32", False), ("asm", 2048, "f32", False),
+    ("asm", 64, "f32", True), ("asm", 512, "f16", False), ("fresnel", 1024, "bf16", False),
+    ("asm", 16, "f32", False)])
+def test_fused_intensity_equals_propagate_then_intensity(ctx, kind, n, prec, nopad):
+    """cwo_asm_intensity / cwo_fresnel_intensity store |u|^2 from the last pass: bit for
+    bit the intensity of the complex result of the same propagation, and within the
+    propagation's bound of the oracle's |u|^2 (relative L2 <= 2e-5: twice the field's
+    1e-5 for FP32; 6e-3 for 16-bit storage)."""
+    import torch
+    u_np = W.rectangles_field(n, 60 + n) if n >= 64 else W.uniform_random_field(n, 60 + n)
+    u = torch.from_numpy(u_np).cuda()
+    args = (8e-6, 8e-6, 532e-9, 0.05)
+    note("fused intensity %s n=%d %s nopad=%s" % (kind, n, prec, nopad))
+    prop = ctx.asm if kind == "asm" else ctx.fresnel
+    fused = ctx.asm_intensity if kind == "asm" else ctx.fresnel_intensity
+    y = prop(u, *args, precision=prec, nopad=nopad)
+    sep = ctx.intensity(y)
+    got = fused(u, *args, precision=prec, nopad=nopad)
+    torch.cuda.synchronize()
+    assert got.dtype == torch.float32 and tuple(got.shape) == (n, n)
+    assert torch.equal(got, sep)
+    ref = np.abs(D.propagate(u_np, D.ASM if kind == "asm" else D.FRESNEL, *args, nopad=nopad)) ** 2
+    rl = D.rel_l2(got.cpu().numpy().astype(np.float64), ref)
+    note("fused intensity %s n=%d %s rel_l2 vs oracle %.3e" % (kind, n, prec, rl))
+    assert rl <= (2e-5 if prec == "f32" else 6e-3)
