@@ -313,6 +313,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (a plain copy "
                          "kernel of known traffic, to calibrate profiler byte counters)")
+    ap.add_argument("--pls-points", type=int, default=0,
+                    help="time only the point-light-source hologram of the 2048^2 geometry with "
+                         "this many points (--steps calls after --warmup) and print one line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -325,6 +328,23 @@ def main():
     import numpy as np
     import torch
     from paper_1107_5578_amd import cwo, workloads as W
+
+    if args.pls_points > 0:
+        pc = W.PLS_2048
+        dev = torch.device("cuda:0")
+        ctx = cwo.Context(0)
+        stream = torch.cuda.current_stream(dev)
+        pts = torch.from_numpy(W.pls_points(args.pls_points, 7)).to(dev)
+        h = torch.empty((pc.n, pc.n), dtype=torch.float32, device=dev)
+        ms = time_call(torch, stream, lambda: ctx.pls_cgh(pts, pc.n, pc.n, pc.pitch, pc.pitch,
+                                                          pc.wavelength, pc.ox, pc.oy, pc.oz,
+                                                          out=h), args.steps, args.warmup)
+        terms = args.pls_points * pc.n * pc.n
+        print(json.dumps({"metric": "PLS hologram terms/s at 2048^2", "points": args.pls_points,
+                          "ms": round(ms, 4), "terms_per_s": float("%.4g" % (terms / (ms * 1e-3))),
+                          "steps": args.steps, "warmup": args.warmup}), flush=True)
+        ctx.close()
+        return
 
     cfg = W.PLANE_2048
     n = args.n or cfg.n
