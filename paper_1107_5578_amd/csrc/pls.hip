@@ -2,12 +2,12 @@
 // Fresnel wavelets over N object points (Sec. 2.4, Eqs. pls_fre and pls_fre_cgh).
 //
 // Every (pixel, point) term evaluates its phase r^2/(2 lambda z_j) in revolutions in
-// FP64, reduces it modulo one in FP64 and takes the hardware cosine (and sine) of the
-// FP32 remainder, which work in revolutions. The sum is arithmetic-bound (no transform,
-// O(N Nx Ny) terms): points are staged through LDS in chunks read by all threads at
-// once (one broadcast address per wavefront), each thread owns kPlsPx pixels of a row,
-// and the row's y distance to the point is shared by them. Partial sums over a chunk
-// are FP32, the running sum across chunks FP64.
+// FP64, takes its fractional part in FP64 (one exact instruction) and the hardware
+// cosine (and sine) of that remainder rounded to FP32, which work in revolutions. The sum
+// is arithmetic-bound (no transform, O(N Nx Ny) terms): points are staged through LDS in
+// chunks read by all threads at once (one broadcast address per wavefront), each thread
+// owns kPlsPx pixels of a row, and the row's y distance to the point is shared by them.
+// Partial sums over a chunk are FP32, the running sum across chunks FP64.
 
 #include "kernel_common.hpp"
 
@@ -21,9 +21,10 @@ constexpr int kPlsTile = kPlsThreads * kPlsPx;  // pixels of one row per block
 constexpr int kPlsChunk = 512;                  // points per LDS stage (16 KB)
 
 // One object point in absolute coordinates: x_j, y_j [m], c_j = 1/(2 lambda z_j)
-// [revolutions per m^2] and its amplitude A_j.
+// [revolutions per m^2] and its amplitude A_j (32 bytes).
 struct PlsPoint {
-    double x, y, c, a;
+    double x, y, c;
+    float a, pad;
 };
 
 __global__ __launch_bounds__(256) void k_pls_points(const float4* __restrict__ in, int n,
@@ -32,8 +33,8 @@ __global__ __launch_bounds__(256) void k_pls_points(const float4* __restrict__ i
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 p = in[i];
-    out[i] = PlsPoint{ox + (double)p.x, oy + (double)p.y, 0.5 / (lam * (oz + (double)p.z)),
-                      (double)p.w};
+    out[i] = PlsPoint{ox + (double)p.x, oy + (double)p.y, 0.5 / (lam * (oz + (double)p.z)), p.w,
+                      0.f};
 }
 
 // FIELD false: out is float [ny][nx], I = sum_j A_j cos(2 pi r_j).
@@ -65,12 +66,12 @@ __global__ __launch_bounds__(kPlsThreads) void k_pls(const PlsPoint* __restrict_
             const PlsPoint q = sp[j];
             const double dy = y - q.y;
             const double dy2 = dy * dy;
-            const float a = (float)q.a;
+            const float a = q.a;
 #pragma unroll
             for (int k = 0; k < kPlsPx; ++k) {
                 const double dx = xs[k] - q.x;
                 const double t = q.c * fma(dx, dx, dy2);
-                const float r = (float)(t - rint(t));  // [-0.5, 0.5] revolutions
+                const float r = (float)__builtin_amdgcn_fract(t);  // [0, 1) revolutions
                 cre_f[k] = fmaf(a, __builtin_amdgcn_cosf(r), cre_f[k]);
                 if constexpr (FIELD) cim_f[k] = fmaf(a, __builtin_amdgcn_sinf(r), cim_f[k]);
             }
