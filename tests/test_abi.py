@@ -188,3 +188,15 @@ def test_autotune_null_context():
     t = cwo.Tuning()
     assert cwo.load().cwo_autotune(None, ctypes.byref(p), 1, None, None, None,
                                    ctypes.byref(t)) == cwo.CWO_ERR_INVALID
+
+
+def test_point_light_source_and_fused_intensity_null_context():
+    lib = cwo.load()
+    pp = cwo.PlsParams(64, 32, 4e-6, 4e-6, 633e-9, 0.0, 0.0, 0.2)
+    assert ctypes.sizeof(cwo.PlsParams) == 56
+    for fn in (lib.cwo_pls_cgh, lib.cwo_pls_field):
+        assert fn(None, ctypes.byref(pp), None, 0, None, None) == cwo.CWO_ERR_INVALID
+        assert fn(None, None, None, 0, None, None) == cwo.CWO_ERR_INVALID
+    p = cwo.make_params(64, 64, 10e-6, z=0.1)
+    for fn in (lib.cwo_asm_intensity, lib.cwo_fresnel_intensity):
+        assert fn(None, ctypes.byref(p), None, None, None) == cwo.CWO_ERR_INVALID
