@@ -51,10 +51,13 @@ struct AsmH {
 //     (z/lambda) sqrt(1 - s) = zl - zl*a/2 - zl*b/2 - zl*T(s),  s = a + b,
 // a = (lambda fx)^2 per column, b = (lambda fy)^2 per row. Every large term is
 // reduced modulo one revolution in FP64 before it is rounded to FP32; T(s) is the
-// power series sum_{n>=2} c_n s^n (c_n = (2n-3)!!/(2^n n!)) to n = 9, whose
-// truncation error is below 3e-12 relative for s <= 0.05. The hardware sine and
-// cosine take the reduced phase in revolutions.
-struct AsmHFast {
+// power series sum_{n>=2} c_n s^n (c_n = (2n-3)!!/(2^n n!)) to n = NT: to n = 9 its
+// truncation error is below 3e-12 relative for s <= 0.05, and the launcher takes NT = 4
+// where zl times the rest of the series is below 2^-28 revolution on the whole grid.
+// The hardware sine and cosine take the reduced phase in revolutions.
+template <int NT>
+struct AsmHFastN {
+    static_assert(NT == 4 || NT == 9, "series length");
     double lam_dfx, lam_dfy;  // lambda/(Mx dx), lambda/(My dy)
     double zl, half_zl;       // z/lambda, z/(2 lambda)
     float c0;                 // zl reduced to [-0.5, 0.5]
@@ -79,21 +82,27 @@ struct AsmHFast {
     }
     __device__ __forceinline__ float2 operator()(const Col& c, const Row& rw) const {
         const double s = c.a + rw.b;
-        double poly = 715.0 / 65536.0;
-        poly = fma(poly, s, 429.0 / 32768.0);
-        poly = fma(poly, s, 33.0 / 2048.0);
-        poly = fma(poly, s, 21.0 / 1024.0);
-        poly = fma(poly, s, 7.0 / 256.0);
-        poly = fma(poly, s, 5.0 / 128.0);
+        double poly;
+        if constexpr (NT == 9) {
+            poly = 715.0 / 65536.0;
+            poly = fma(poly, s, 429.0 / 32768.0);
+            poly = fma(poly, s, 33.0 / 2048.0);
+            poly = fma(poly, s, 21.0 / 1024.0);
+            poly = fma(poly, s, 7.0 / 256.0);
+            poly = fma(poly, s, 5.0 / 128.0);
+        } else {
+            poly = 5.0 / 128.0;
+        }
         poly = fma(poly, s, 1.0 / 16.0);
         poly = fma(poly, s, 1.0 / 8.0);
-        // zl*b/2 + zl*T(s), reduced, in FP64
+        // zl*b/2 + zl*T(s), reduced (the exact fractional part), in FP64
         const double u = fma(zl * (s * s), poly, rw.hb);
-        float r = c.ca - (float)(u - rint(u));
+        float r = c.ca - (float)__builtin_amdgcn_fract(u);
         r -= rintf(r);
         return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
     }
 };
+using AsmHFast = AsmHFastN<9>;
 
 struct FresnelH {
     const float2* __restrict__ hx;  // Mx entries, carries the constant C

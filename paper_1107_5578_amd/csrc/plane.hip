@@ -330,14 +330,25 @@ hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t p
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
     const double smax = sx * sx + sy * sy;
     if (smax <= kAsmFastMaxS) {
-        AsmHFast hf;
-        hf.lam_dfx = a.lam * a.dfx;
-        hf.lam_dfy = a.lam * a.dfy;
-        hf.zl = a.zl;
-        hf.half_zl = 0.5 * a.zl;
-        hf.c0 = (float)(a.zl - std::nearbyint(a.zl));
-        hf.mx = mx;
-        hf.my = my;
+        auto fill = [&](auto& hf) {
+            hf.lam_dfx = a.lam * a.dfx;
+            hf.lam_dfy = a.lam * a.dfy;
+            hf.zl = a.zl;
+            hf.half_zl = 0.5 * a.zl;
+            hf.c0 = (float)(a.zl - std::nearbyint(a.zl));
+            hf.mx = mx;
+            hf.my = my;
+        };
+        // the series to s^4 suffices when |zl| times its remainder, at most
+        // c_5 smax^5/(1 - smax) with c_5 = 7/256, stays below 2^-28 revolution
+        const double s5 = smax * smax * smax * smax * smax;
+        if (std::fabs(a.zl) * (7.0 / 256.0) * s5 / (1.0 - smax) <= std::ldexp(1.0, -28)) {
+            AsmHFastN<4> hf;
+            fill(hf);
+            return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
+        }
+        AsmHFastN<9> hf;
+        fill(hf);
         return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
     }
     AsmH hf{a.dfx, a.dfy, a.lam, a.zl, mx, my};
