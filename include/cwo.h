@@ -30,7 +30,12 @@
  * Graph capture: once a call with the same parameters (and, for z-stacks and batches, the
  * same plane count) has run on a context, a propagation call only enqueues kernels on its
  * stream, so it can be captured into a HIP graph and replayed; the first call allocates
- * scratch and tables and must run outside the capture. Profiling must be off.
+ * scratch and tables and must run outside the capture. Profiling must be off. A graph
+ * keeps the scratch, table and Fresnel-factor addresses it captured: a later call on the
+ * same context that needs more scratch (a larger plane, more planes or points) grows the
+ * buffer and frees the old one, and more distinct Fresnel parameter sets than the factor
+ * cache holds evict old factors, after which such a graph must not be replayed. Calls
+ * that fit the captured sizes, as in a serving loop of fixed shapes, leave it valid.
  *
  * Errors: every call returns a cwo_status. Parameters are validated before anything is
  * launched. A device error makes the context return CWO_ERR_DEVICE from then on.

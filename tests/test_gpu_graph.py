@@ -100,3 +100,38 @@ def test_batch_graph_replay(ctx):
         torch.cuda.synchronize()
         for f, o in zip(ins, outs):
             assert torch.equal(o, ctx.asm(f, 8e-6, 8e-6, 532e-9, 0.1)), rep
+
+
+def test_point_light_source_and_fused_intensity_graph_replay(ctx):
+    """The hologram sum and the fused-intensity propagation captured and replayed: each
+    replay equals an eager call on the replay's inputs (eager calls between replays use no
+    more points and no larger plane, so the captured scratch stays in place)."""
+    import torch
+    n, count = 256, 700
+    clouds = [torch.from_numpy(W.pls_points(count, 950 + k, half_extent=2e-4)).cuda()
+              for k in range(3)]
+    pts = clouds[0].clone()
+    holo = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    src = fields(n, 3, 960)
+    u = src[0].clone()
+    inten = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    args = (n, n, 4e-6, 4e-6, 633e-9, 1e-4, 0.0, 0.1)
+    ctx.pls_cgh(pts, *args, out=holo)
+    ctx.asm_intensity(u, 8e-6, 8e-6, 532e-9, 0.2, out=inten)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.pls_cgh(pts, *args, out=holo)
+        ctx.asm_intensity(u, 8e-6, 8e-6, 532e-9, 0.2, out=inten)
+    for rep in range(3):
+        pts.copy_(clouds[rep])
+        u.copy_(src[rep])
+        g.replay()
+        ctx.pls_cgh(clouds[(rep + 1) % 3][: count // 2].contiguous(), *args)  # eager, fewer points
+        ctx.asm(src[(rep + 1) % 3], 8e-6, 8e-6, 532e-9, 0.3)
+        torch.cuda.synchronize()
+        ref_h = ctx.pls_cgh(clouds[rep], *args)
+        ref_i = ctx.asm_intensity(src[rep], 8e-6, 8e-6, 532e-9, 0.2)
+        torch.cuda.synchronize()
+        assert torch.equal(holo, ref_h), rep
+        assert torch.equal(inten, ref_i), rep
