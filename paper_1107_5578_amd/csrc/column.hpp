@@ -105,6 +105,9 @@ struct AsmHFastN {
 using AsmHFast = AsmHFastN<9>;
 
 struct FresnelH {
+    // the per-row factors are table reads: the column pass issues them before its forward
+    // transform, so their latency hides behind it
+    static constexpr bool kRowsEarly = true;
     const float2* __restrict__ hx;  // Mx entries, carries the constant C
     const float2* __restrict__ hy;  // My entries
     struct Col {
@@ -119,6 +122,13 @@ struct FresnelH {
         return cmul(c.h, rw.h);
     }
 };
+
+// Transfer functions whose per-row factors are memory reads say so with kRowsEarly.
+template <class HF>
+constexpr bool rows_early() {
+    if constexpr (requires { HF::kRowsEarly; }) return HF::kRowsEarly;
+    else return false;
+}
 
 // Column pass: forward FFT of COLS columns, multiplication by the transfer function,
 // inverse FFT, in place; one (plane, column tile) item per block.
@@ -162,10 +172,19 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     typename HF::Col hc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
+    // (at M = 8192 the extra registers cost more than the hidden latency: measured)
+    constexpr bool EARLY = rows_early<HF>() && M <= 4096;
+    typename HF::Row hre[EARLY ? E : 1];
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) hre[r] = hf.row(j + r * T);
+    }
     fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        const typename HF::Row hr = hf.row(j + r * T);
+        typename HF::Row hr;
+        if constexpr (EARLY) hr = hre[r];
+        else hr = hf.row(j + r * T);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             float2 h = hf(hc[p], hr);
