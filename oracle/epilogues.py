@@ -12,11 +12,11 @@ may import this module; it shares nothing with the product library.
 
 Readings (listed in DESIGN.md):
 
-* The epilogues run on complex64 fields in FP32, as the library computes them:
-  I = re*re + im*im and the scale (I - min) * (top / (max - min)) each rounded to
-  nearest in FP32 in that order; the 8-bit image is that value rounded to the nearest
-  integer (ties to even) and clamped to [0, 255]. These FP32 definitions decide the
-  8-bit codes, so the GPU is compared with them bit for bit.
+* The epilogues run on complex64 fields in FP32: I = re*re + im*im, and Eq. norm
+  evaluated in the order it is written, (I - min), then / (max - min), then * top, each
+  operation rounded to nearest in FP32; the 8-bit image is that value rounded to the
+  nearest integer (ties to even) and clamped to [0, 255]. These FP32 definitions decide
+  the 8-bit codes, so the GPU is compared with them bit for bit.
 * A constant field (max == min) scales to 0.
 * The phase lies in [-pi, pi]; the sign of a zero imaginary part picks the end.
 """
@@ -34,14 +34,16 @@ def intensity(u: np.ndarray) -> np.ndarray:
 
 
 def scale(i: np.ndarray, top: float = 255.0) -> np.ndarray:
-    """(I - min)/(max - min) * top in FP32 (0 where max == min)."""
+    """Eq. norm, (I - min)/(max - min) * top, in FP32 in the printed order: the
+    difference, the quotient by the range, the product with top, each rounded to
+    nearest (0 where max == min)."""
     i = np.asarray(i, dtype=np.float32)
     mn = np.float32(i.min())
     mx = np.float32(i.max())
     if mx == mn:
         return np.zeros_like(i)
-    f = np.float32(top) / np.float32(mx - mn)
-    return ((i - mn) * f).astype(np.float32)
+    rng = np.float32(mx - mn)
+    return (((i - mn) / rng) * np.float32(top)).astype(np.float32)
 
 
 def scale_u8(i: np.ndarray, top: float = 255.0) -> np.ndarray:

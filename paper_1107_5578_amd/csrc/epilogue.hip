@@ -4,9 +4,9 @@
 // grid-stride over n elements.
 //
 // The FP32 operation order is fixed (products and sums rounded separately: contraction
-// into fused multiply-adds is switched off where it matters; the scale as
-// (I - min) * (top / (max - min))), so the 8-bit codes, which floating point decides, are
-// reproducible.
+// into fused multiply-adds is switched off where it matters; the scale in the order Eq.
+// norm prints it, (I - min), then / (max - min) (IEEE division), then * top), so the
+// 8-bit codes, which floating point decides, are reproducible.
 
 #include "kernel_common.hpp"
 
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_minmax_partial(const float* __r
     }
 }
 
-// mm[0] = min, mm[1] = max over the partials; mm[2] = top / (max - min) (0 if max == min)
+// mm[0] = min, mm[1] = max over the partials; mm[2] = max - min; mm[3] = top
 __global__ __launch_bounds__(kEpiThreads) void k_minmax_final(const float* __restrict__ part,
                                                               int np, float top,
                                                               float* __restrict__ mm) {
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_minmax_final(const float* __res
 #pragma clang fp contract(off)
         mm[0] = lo[0];
         mm[1] = hi[0];
-        mm[2] = (hi[0] == lo[0]) ? 0.0f : top / (hi[0] - lo[0]);  // correctly rounded
+        mm[2] = hi[0] - lo[0];
+        mm[3] = top;
     }
 }
 
@@ -105,11 +106,12 @@ template <bool U8>
 __global__ __launch_bounds__(kEpiThreads) void k_scale(const float* __restrict__ in, size_t n,
                                                        const float* __restrict__ mm,
                                                        void* __restrict__ out) {
-    const float mn = mm[0], f = mm[2];
+    const float mn = mm[0], range = mm[2], top = mm[3];
     for (size_t i = (size_t)blockIdx.x * kEpiThreads + threadIdx.x; i < n;
          i += (size_t)gridDim.x * kEpiThreads) {
 #pragma clang fp contract(off)
-        const float v = (in[i] - mn) * f;
+        // a constant field (max == min) scales to 0
+        const float v = range == 0.0f ? 0.0f : ((in[i] - mn) / range) * top;
         if constexpr (U8) {
             const float q = fminf(fmaxf(rintf(v), 0.0f), 255.0f);
             static_cast<uint8_t*>(out)[i] = (uint8_t)q;

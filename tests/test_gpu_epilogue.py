@@ -52,6 +52,21 @@ def test_intensity_and_scale_bit_exact(ctx, n):
     assert np.array_equal(s1.view(np.uint32), P.scale(i_np, 1.0).view(np.uint32))
 
 
+def test_scale_printed_order_case(ctx):
+    # a value whose Eq. norm result lies just above 226.5 in the printed order (code 227)
+    # and exactly on 226.5 when top/(max - min) is formed first (code 226)
+    import torch
+    arr = np.array([0.7443469762802124, 1.8845739364624023, 2.028046131134033] * 1000,
+                   dtype=np.float32)
+    note("epilogue printed-order case")
+    t = torch.from_numpy(arr).cuda()
+    s = ctx.scale(t).cpu().numpy()
+    q = ctx.scale(t, 255.0, u8=True).cpu().numpy()
+    assert np.array_equal(s.view(np.uint32), P.scale(arr).view(np.uint32))
+    assert np.array_equal(q, P.scale_u8(arr))
+    assert q[1] == 227
+
+
 def test_scale_degenerate_and_errors(ctx):
     import torch
     from paper_1107_5578_amd import cwo

@@ -321,3 +321,35 @@ def test_gs_iteration_composition():
     assert np.allclose(np.abs(u1), a1, rtol=1e-14, atol=0)
     v = D.asm(u0, 8e-6, 8e-6, 532e-9, 0.02)
     assert abs(e0 - np.linalg.norm(np.abs(v) - a2) / np.linalg.norm(a2)) < 1e-15
+
+
+def test_gs_error_hand_values():
+    # |v| = (5, 0, 1) against a = (5, 2, 1): the difference is (0, -2, 0), so
+    # E = 2 / sqrt(25 + 4 + 1)
+    v = np.array([3 + 4j, 0, 1j])
+    a = np.array([5.0, 2.0, 1.0])
+    assert gs.error(v, a) == pytest.approx(2 / math.sqrt(30), rel=1e-15)
+    # the amplitude alone counts: any phase on the target amplitude gives 0
+    ph = np.exp(1j * np.array([0.3, -2.0, 3.1]))
+    assert gs.error(a * ph, a) < 1e-15  # |a e^{i phi}| rounds to within an ulp of a
+    # a zero field and a field of twice the amplitude are both at distance ||a||
+    assert gs.error(np.zeros(3), a) == 1.0
+    assert gs.error(2 * a * ph, a) == pytest.approx(1.0, rel=1e-15)
+    # 2-D arrays: the norm runs over every element
+    assert gs.error(np.array([[1j, 0], [0, 0]]), np.array([[1.0, 1.0], [1.0, 1.0]])) == \
+        pytest.approx(math.sqrt(3) / 2, rel=1e-15)
+
+
+def test_gs_iteration_at_zero_distance_is_a_fixed_point():
+    # ASM at z = 0 is the identity, so from u0 = A1 exp(i phi) the step returns u0 and
+    # E_0 = ||A1 - A2|| / ||A2||, here from hand values on a 16x16 grid with two levels
+    n = 16
+    a1 = np.full((n, n), 2.0)
+    a2 = np.full((n, n), 1.0)
+    a2[: n // 2] = 3.0
+    phi = np.linspace(-3.0, 3.0, n * n).reshape(n, n)
+    u0 = a1 * np.exp(1j * phi)
+    u1, e0 = gs.iteration(u0, a1, a2, 8e-6, 532e-9, 0.0)
+    assert np.allclose(u1, u0, rtol=0, atol=1e-13)
+    # half the pixels differ by 1, half by 1; ||A2||^2 = n^2/2 * (9 + 1)
+    assert e0 == pytest.approx(math.sqrt(n * n) / math.sqrt(n * n / 2 * 10), rel=1e-13)

@@ -49,3 +49,52 @@ def test_polar_round_trip():
     assert np.allclose(np.abs(u), a, rtol=1e-14)
     assert np.allclose(np.angle(u), phi, atol=1e-14)
     assert np.allclose(P.polar(phi), np.exp(1j * phi), atol=1e-15)
+
+
+def _round32(q):
+    """Nearest float32 to the exact rational q, ties to even (independent of numpy's
+    float32 arithmetic: neighbours compared in exact rational arithmetic)."""
+    from fractions import Fraction
+
+    c = np.float32(float(q))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - q)
+        if best is None or d < best[0] or (d == best[0] and (cand.view(np.uint32) & 1) == 0):
+            best = (d, cand)
+    return best[1]
+
+
+def _scale_exact_order(i, mn, mx, top):
+    """Eq. norm with each operation of its printed order rounded once to FP32."""
+    from fractions import Fraction
+
+    F = Fraction
+    d = _round32(F(float(i)) - F(float(mn)))
+    r = _round32(F(float(mx)) - F(float(mn)))
+    q = _round32(F(float(d)) / F(float(r)))
+    return _round32(F(float(q)) * F(float(top)))
+
+
+def test_scale_follows_the_printed_order_where_orders_round_apart():
+    # (I - min)/(max - min) * 255 lands just above 226.5 in the printed order and exactly
+    # on 226.5 with the factor 255/(max - min) formed first: the two orders give 8-bit
+    # codes 227 and 226, so this case tells them apart.
+    mn, i, mx = np.float32(0.7443469762802124), np.float32(1.8845739364624023), np.float32(2.028046131134033)
+    arr = np.array([mn, i, mx], dtype=np.float32)
+    want = _scale_exact_order(i, mn, mx, np.float32(255))
+    got = P.scale(arr)
+    assert got[1] == want
+    other = np.float32(np.float32(i - mn) * np.float32(np.float32(255) / np.float32(mx - mn)))
+    assert other != want and np.rint(other) != np.rint(want)
+    assert P.scale_u8(arr)[1] == 227
+    assert got[0] == 0.0 and got[2] == 255.0
+
+
+def test_scale_matches_per_operation_rounding_on_random_values():
+    rng = np.random.default_rng(11)
+    arr = rng.uniform(0.3, 7.0, 200).astype(np.float32)
+    mn, mx = arr.min(), arr.max()
+    got = P.scale(arr, 200.0)
+    for k in range(0, 200, 7):
+        assert got[k] == _scale_exact_order(arr[k], mn, mx, np.float32(200.0))
