@@ -113,9 +113,12 @@ typedef struct {
 
 typedef struct cwo_ctx cwo_ctx; /* opaque */
 
-/* Create a context on HIP device `device`. hbm_budget_bytes bounds the scratch memory the
- * context may hold at once (0 = no bound). Returns CWO_ERR_INVALID for a null ctx pointer
- * or a bad device ordinal, CWO_ERR_DEVICE if the device cannot be used. */
+/* Create a context on HIP device `device`. hbm_budget_bytes (0 = no bound) bounds device
+ * memory: the workspace of the synchronous calls stays within it (a call that would need
+ * more returns CWO_ERR_NOMEM), and the serving scheduler admits a request only while the
+ * fields of the admitted, unfinished requests plus everything the context holds (see
+ * cwo_memory_held) stay within it. Returns CWO_ERR_INVALID for a null ctx pointer or a bad
+ * device ordinal, CWO_ERR_DEVICE if the device cannot be used. */
 cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes);
 
 /* Finish every submitted job, wait for all work the context launched, stop its scheduler
@@ -308,15 +311,25 @@ cwo_status cwo_pls_field(cwo_ctx* ctx, const cwo_pls_params* p, const float* poi
 /* ---- serving (continuous batching) ----------------------------------------------------
  * cwo_submit queues one job and returns at once with a ticket; a scheduler thread of the
  * context admits queued jobs in arrival order when one of its 4 slots (each with its own
- * HIP stream, scratch and Fresnel-factor cache) is free and the job's footprint fits the
- * context's HBM budget next to the jobs already running. A free slot takes the head job and
- * the following ones that fit (up to 8) as one batch, run back to back on its stream (jobs
- * on the same field form a z-stack), so requests that arrive while others run are admitted
- * as slots and memory free up, and their work overlaps on the device.
- * Footprint of a job: its input and output fields plus its padded scratch plane
- * (16 nx ny + 8 ny 2nx bytes for complex64 storage). A job larger than the whole budget is
- * rejected with CWO_ERR_NOMEM at submit; one that merely does not fit yet stays queued.
- * The caller keeps in/out alive until the ticket reports done. Thread-safe. */
+ * HIP stream, scratch and Fresnel-factor cache) is free and the job fits the context's HBM
+ * budget: the input and output fields of every admitted, unfinished job, all memory the
+ * context holds, and what the new batch adds to its slot's scratch together stay within the
+ * budget (idle slots free their scratch first when memory is short). A free slot takes the
+ * head job and the following ones that fit (up to 8) as one batch, run back to back on its
+ * stream (complex64 jobs on the same field form a z-stack), so requests that arrive while
+ * others run are admitted as slots and memory free up, and their work overlaps on the
+ * device. Submit and poll never wait for the scheduler's launches or allocations.
+ * Footprint of a job (reported by cwo_ticket_info): its input and output fields plus its
+ * padded scratch plane (16 nx ny + 8 ny 2nx bytes for complex64 storage). A job larger than
+ * the whole budget is rejected with CWO_ERR_NOMEM at submit; one that merely does not fit
+ * yet stays queued, and fails with CWO_ERR_NOMEM only if it cannot fit even with every slot
+ * idle (memory held by the synchronous calls' workspace).
+ * Ordering: cwo_submit does not order the job after any stream, so its input must be
+ * complete when it is submitted (e.g. after a synchronisation). cwo_submit_after makes the
+ * job's first kernel wait for all work enqueued on hip_stream before the call (an event
+ * the library records there), so a field produced by asynchronous kernels on that stream
+ * can be submitted at once. The caller keeps in/out alive, and does not touch out, until
+ * the ticket reports done. Thread-safe. */
 
 /* Ticket states reported by cwo_poll: 0 queued, 1 running, 2 done, < 0 the job's error. */
 typedef struct {
@@ -326,12 +339,18 @@ typedef struct {
 } cwo_ticket;
 
 cwo_status cwo_submit(cwo_ctx* ctx, const cwo_job* job, uint64_t* ticket);
+cwo_status cwo_submit_after(cwo_ctx* ctx, const cwo_job* job, void* hip_stream,
+                            uint64_t* ticket);
 cwo_status cwo_poll(cwo_ctx* ctx, uint64_t ticket, int32_t* state);
 cwo_status cwo_ticket_info(cwo_ctx* ctx, uint64_t ticket, cwo_ticket* info);
 /* Forget a finished ticket (CWO_ERR_INVALID while it is queued or running). */
 cwo_status cwo_release(cwo_ctx* ctx, uint64_t ticket);
 /* Wait until every submitted job has finished; returns the context's sticky status. */
 cwo_status cwo_drain(cwo_ctx* ctx);
+/* Bytes of device memory the context holds now: twiddle tables, the synchronous calls'
+ * workspace and every serving slot's scratch and Fresnel factors (not the caller's fields).
+ * Between the scheduler's admissions it stays within the budget. */
+cwo_status cwo_memory_held(cwo_ctx* ctx, size_t* bytes);
 
 /* Validate a parameter set for `kind` without touching any device: the same checks the
  * propagation calls run first. Returns CWO_OK, CWO_ERR_INVALID or CWO_ERR_UNSUPPORTED. */

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <chrono>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <list>
@@ -63,9 +64,15 @@ struct Workspace {
     Buffer pls;                       // FP64 point records of the point-light-source sums
     std::list<FresnelEntry> fresnel;  // most recently used first
     size_t budget = 0;                // 0: unbounded (serving slots are bounded by admission)
-    size_t held() const {
-        return scratch.bytes + fwork.bytes + ftab.bytes + gsnum.bytes + rwork.bytes +
-               fourier.bytes + ework.bytes + pls.bytes;
+    // The one stream that uses this workspace (a serving slot's), or null when calls on
+    // any stream may have used it: replacing a buffer first waits for that stream, or for
+    // the whole device.
+    hipStream_t owner = nullptr;
+    // bytes of device memory held (buffers and Fresnel factors), readable from any thread
+    std::atomic<size_t> total{0};
+    size_t held() const { return total.load(); }
+    hipError_t quiesce() const {
+        return owner ? hipStreamSynchronize(owner) : hipDeviceSynchronize();
     }
     void release() {
         for (Buffer* b : {&scratch, &fwork, &ftab, &gsnum, &rwork, &fourier, &ework, &pls}) {
@@ -75,13 +82,15 @@ struct Workspace {
         }
         for (auto& e : fresnel) (void)hipFree(e.h);
         fresnel.clear();
+        total = 0;
     }
 };
 
 struct Ticket {
     cwo_job job;
-    int32_t state = 0;      // 0 queued, 1 running, 2 done, < 0 error status
-    size_t footprint = 0;   // bytes reserved from admission to completion
+    int32_t state = 0;         // 0 queued, 1 running, 2 done, < 0 error status
+    size_t footprint = 0;      // bytes reserved from admission to completion
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream (null: no ordering)
     double t_submit = 0, t_start = 0, t_done = 0;
 };
 
@@ -104,21 +113,27 @@ struct TuneKey {
     }
 };
 
+// Serving slots per context (each its own stream and workspace).
+constexpr int kSlots = 4;
+
 struct cwo_ctx {
     int device = 0;
     size_t budget = 0;
     std::mutex mu;  // synchronous calls, twiddle tables, profiling
     cwo_status sticky = CWO_OK;
     std::map<int, float2*> twiddles;  // FP32 exp(-2 pi i k / M) per M
+    std::atomic<size_t> twiddle_bytes{0};
     Workspace ws;                     // workspace of the synchronous calls
-    // serving
+    // serving; lock order: qmu before mu
     std::mutex qmu;  // tickets, queue, admission state
     std::condition_variable qcv;
     std::map<uint64_t, Ticket> tickets;
     std::deque<uint64_t> queue;
     uint64_t next_ticket = 1;
-    size_t reserved = 0;  // footprint of admitted, unfinished requests
-    std::vector<Slot> slots;
+    size_t reserved = 0;  // input and output bytes of admitted, unfinished requests
+    Slot slots[kSlots];
+    bool slots_ready = false;
+    std::vector<hipEvent_t> ready_pool;  // spare events for submit-time ordering
     std::thread worker;
     bool stop = false;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -209,9 +224,12 @@ const float2* twiddle_table(cwo_ctx* c, int m, hipStream_t s, cwo_status* st) {
         return nullptr;
     }
     c->twiddles[m] = tw;
+    c->twiddle_bytes += sizeof(float2) * (size_t)m;
     return tw;
 }
 
+// Grow b to at least `bytes` (contents are not kept). The old allocation may still be in
+// use by queued kernels, so growing first waits for the workspace's stream (or device).
 void* ensure(cwo_ctx* c, Workspace& ws, Buffer& b, size_t bytes, cwo_status* st) {
     if (b.bytes >= bytes) return b.p;
     if (ws.budget && ws.held() - b.bytes + bytes > ws.budget) {
@@ -219,11 +237,12 @@ void* ensure(cwo_ctx* c, Workspace& ws, Buffer& b, size_t bytes, cwo_status* st)
         return nullptr;
     }
     if (b.p) {
-        if (hipDeviceSynchronize() != hipSuccess) {
+        if (ws.quiesce() != hipSuccess) {
             *st = dev_fail(c);
             return nullptr;
         }
         (void)hipFree(b.p);
+        ws.total -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
     }
@@ -233,6 +252,7 @@ void* ensure(cwo_ctx* c, Workspace& ws, Buffer& b, size_t bytes, cwo_status* st)
         return nullptr;
     }
     b.bytes = bytes;
+    ws.total += bytes;
     return b.p;
 }
 
@@ -353,11 +373,12 @@ const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hip
     if (ws.fresnel.size() >= kFresnelCacheEntries) {
         FresnelEntry old = ws.fresnel.back();
         ws.fresnel.pop_back();
-        if (hipDeviceSynchronize() != hipSuccess) {
+        if (ws.quiesce() != hipSuccess) {
             *st = dev_fail(c);
             return nullptr;
         }
         (void)hipFree(old.h);
+        ws.total -= sizeof(float2) * (size_t)(old.key.mx + old.key.my);
     }
     FresnelEntry e;
     e.key = key;
@@ -365,6 +386,7 @@ const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hip
         *st = CWO_ERR_NOMEM;
         return nullptr;
     }
+    ws.total += sizeof(float2) * len;
     cwo::FresnelPlanes fp;
     std::memset(&fp, 0, sizeof(fp));
     fp.mx = key.mx;
@@ -388,6 +410,7 @@ const float2* factor_table(cwo_ctx* c, Workspace& ws, const FresnelKey& key, hip
     if (timed(c, CWO_STAGE_TABLES, s, [&] { return cwo::launch_fresnel_planes(work, e.h, fp, s); }) !=
         hipSuccess) {
         (void)hipFree(e.h);
+        ws.total -= sizeof(float2) * len;
         *st = dev_fail(c);
         return nullptr;
     }
@@ -581,10 +604,13 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
     return CWO_OK;
 }
 
+// Jobs that run as one z-stack: the same field and geometry, complex64 storage (z-stacks
+// keep complex64 planes; 16-bit requests run singly).
 bool same_group(const cwo_job& a, const cwo_job& b) {
     return a.in == b.in && a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx &&
            a.p.dy == b.p.dy && a.p.wavelength == b.p.wavelength && a.p.kind == b.p.kind &&
-           a.p.precision == b.p.precision && a.p.flags == b.p.flags;
+           a.p.precision == CWO_PREC_F32 && b.p.precision == CWO_PREC_F32 &&
+           a.p.flags == b.p.flags;
 }
 
 cwo_status validate_jobs(const cwo_job* jobs, int njobs) {
@@ -675,54 +701,130 @@ int batch_run(const cwo_job* jobs, int i, int njobs) {
     return j - i;
 }
 
-cwo_status run_jobs(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int njobs, hipStream_t s) {
-    cwo_status st = CWO_OK;
+// How run_jobs groups a job list: consecutive jobs on one field with one geometry form a
+// z-stack; runs of identical parameters on distinct fields a batch; the rest run singly.
+struct Group {
+    enum Type { SINGLE, ZSTACK, BATCH } type;
+    int i, j;  // jobs [i, j)
+};
+
+std::vector<Group> plan_groups(const cwo_job* jobs, int njobs) {
+    std::vector<Group> gs;
     int i = 0;
     while (i < njobs) {
         int j = i + 1;
         while (j < njobs && same_group(jobs[i], jobs[j])) ++j;
-        if (j - i == 1 && batch_run(jobs, i, njobs) > 1) {
-            j = i + batch_run(jobs, i, njobs);
-            st = batch_locked(c, ws, jobs + i, j - i, s);
-        } else if (j - i == 1) {
+        if (j - i == 1 && batch_run(jobs, i, njobs) > 1)
+            gs.push_back({Group::BATCH, i, i + batch_run(jobs, i, njobs)});
+        else
+            gs.push_back({j - i == 1 ? Group::SINGLE : Group::ZSTACK, i, j});
+        i = gs.back().j;
+    }
+    return gs;
+}
+
+cwo_status run_jobs(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int njobs, hipStream_t s) {
+    for (const Group& gr : plan_groups(jobs, njobs)) {
+        cwo_status st = CWO_OK;
+        const int i = gr.i, n = gr.j - gr.i;
+        if (gr.type == Group::BATCH) {
+            st = batch_locked(c, ws, jobs + i, n, s);
+        } else if (gr.type == Group::SINGLE) {
             st = propagate_locked(c, ws, &jobs[i].p, jobs[i].p.kind, jobs[i].in, jobs[i].out, s);
         } else {
             std::vector<double> z;
             std::vector<void*> outs;
-            for (int k = i; k < j; ++k) {
+            for (int k = gr.i; k < gr.j; ++k) {
                 z.push_back(jobs[k].p.z);
                 outs.push_back(jobs[k].out);
             }
-            st = zstack_locked(c, ws, &jobs[i].p, jobs[i].p.kind, z.data(), j - i, jobs[i].in,
+            st = zstack_locked(c, ws, &jobs[i].p, jobs[i].p.kind, z.data(), n, jobs[i].in,
                                outs.data(), s);
         }
         if (st != CWO_OK) return st;
-        i = j;
     }
     return CWO_OK;
+}
+
+// Largest size of each workspace buffer a job list needs on an unbounded workspace (the
+// serving slots'), and how many Fresnel factor entries it may add.
+struct WsNeed {
+    size_t scratch = 0, fwork = 0, ftab = 0, rwork = 0, factors = 0;
+};
+
+WsNeed jobs_need(cwo_ctx* c, const cwo_job* jobs, int njobs) {
+    WsNeed w;
+    for (const Group& gr : plan_groups(jobs, njobs)) {
+        const cwo_params* p = &jobs[gr.i].p;
+        const Geometry g = geometry(p);
+        const size_t plane = (size_t)g.ny * g.mx;
+        const size_t len = (size_t)(g.mx + g.my);
+        const bool fres = p->kind == CWO_FRESNEL_CONV;
+        const int n = gr.j - gr.i;
+        if (gr.type == Group::ZSTACK) {
+            int zc = std::min(n, cwo::kZChunk);
+            const cwo_tuning t = tuned_for(c, p, p->kind, n);
+            if (t.zchunk > 0) zc = std::min(zc, t.zchunk);
+            w.scratch = std::max(w.scratch, sizeof(float2) * plane * (size_t)(1 + zc));
+            if (fres) {
+                w.ftab = std::max(w.ftab, sizeof(float2) * len * (size_t)zc);
+                w.fwork = std::max(w.fwork, sizeof(double2) * len);
+            }
+        } else {
+            const size_t planes = gr.type == Group::BATCH ? (size_t)std::min(n, cwo::kZChunk) : 1;
+            w.scratch = std::max(w.scratch, elem_bytes(p->precision) * plane * planes);
+            if (p->precision == CWO_PREC_F16_STORAGE)
+                w.rwork = std::max(w.rwork, sizeof(float) * (2 + cwo::kRangeBlocks));
+            if (fres) {
+                w.fwork = std::max(w.fwork, sizeof(double2) * len);
+                w.factors += sizeof(float2) * len;
+            }
+        }
+    }
+    return w;
+}
+
+// Bytes workspace ws would add to hold what `need` asks for (its cache may also evict).
+size_t growth(const Workspace& ws, const WsNeed& need) {
+    auto more = [](size_t have, size_t want) { return want > have ? want - have : 0; };
+    return more(ws.scratch.bytes, need.scratch) + more(ws.fwork.bytes, need.fwork) +
+           more(ws.ftab.bytes, need.ftab) + more(ws.rwork.bytes, need.rwork) + need.factors;
 }
 
 // ---- serving: continuous batching ------------------------------------------------
 //
 // A scheduler thread per context admits queued requests in arrival order when a slot
-// (its own HIP stream, workspace and completion event) is free and the request's
-// footprint fits the HBM budget next to the requests already running; a free slot takes
-// the head request and the following ones that fit (up to kMaxBatch) as one batch, run
-// back to back on its stream (requests on the same field form a z-stack). Slots run
-// concurrently, so work from different arrivals overlaps on the device.
+// (its own HIP stream, workspace and completion event) is free and the request fits the
+// HBM budget: the input and output fields of every admitted, unfinished request, the
+// memory every workspace of the context holds, and what the new batch would add to its
+// slot's workspace, together at most the budget. Idle slots give their workspaces back
+// when memory is short. A free slot takes the head request and the following ones that
+// fit (up to kMaxBatch) as one batch, run back to back on its stream (requests on the same
+// field form a z-stack). Slots run concurrently, so work from different arrivals overlaps
+// on the device. Launching happens outside the queue lock, so submit and poll never wait
+// for kernel launches or allocations.
 
-constexpr int kSlots = 4;
 constexpr int kMaxBatch = 8;
 
 double now_s(const cwo_ctx* c) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - c->t0).count();
 }
 
-// Bytes a request holds from admission to completion: its input and output fields and
-// its padded scratch plane.
+// Bytes of the caller's input and output fields of a request.
+size_t io_bytes(const cwo_params* p) { return 16 * (size_t)p->nx * p->ny; }
+
+// Bytes a request holds from admission to completion when it runs alone: its input and
+// output fields and its padded scratch plane.
 size_t footprint(const cwo_params* p) {
     const Geometry g = geometry(p);
-    return 16 * (size_t)g.nx * g.ny + elem_bytes(p->precision) * (size_t)g.ny * g.mx;
+    return io_bytes(p) + elem_bytes(p->precision) * (size_t)g.ny * g.mx;
+}
+
+// Device memory the context holds: twiddle tables and every workspace.
+size_t held_bytes(cwo_ctx* c) {
+    size_t h = c->twiddle_bytes.load() + c->ws.held();
+    for (const Slot& sl : c->slots) h += sl.ws.held();
+    return h;
 }
 
 void serve_loop(cwo_ctx* c) {
@@ -744,7 +846,11 @@ void serve_loop(cwo_ctx* c) {
                 if (it == c->tickets.end()) continue;
                 it->second.state = (q == hipSuccess) ? 2 : CWO_ERR_DEVICE;
                 it->second.t_done = t;
-                c->reserved -= it->second.footprint;
+                c->reserved -= io_bytes(&it->second.job.p);
+                if (it->second.ready) {
+                    c->ready_pool.push_back(it->second.ready);
+                    it->second.ready = nullptr;
+                }
             }
             if (q != hipSuccess) c->sticky = CWO_ERR_DEVICE;
             sl.running.clear();
@@ -754,35 +860,92 @@ void serve_loop(cwo_ctx* c) {
             if (!sl.running.empty() || c->queue.empty()) continue;
             std::vector<cwo_job> batch;
             std::vector<uint64_t> ids;
-            while (!c->queue.empty() && (int)batch.size() < kMaxBatch) {
-                Ticket& tk = c->tickets[c->queue.front()];
-                if (c->budget && c->reserved + tk.footprint > c->budget) break;  // FIFO: wait
-                c->reserved += tk.footprint;
-                tk.state = 1;
-                tk.t_start = now_s(c);
+            size_t io = 0;
+            bool trimmed = false;
+            for (size_t k = 0; k < c->queue.size() && (int)batch.size() < kMaxBatch; ++k) {
+                const uint64_t id = c->queue[k];
+                const Ticket& tk = c->tickets[id];
                 batch.push_back(tk.job);
-                ids.push_back(c->queue.front());
-                c->queue.pop_front();
+                const WsNeed need = jobs_need(c, batch.data(), (int)batch.size());
+                auto fits = [&] {
+                    return !c->budget || c->reserved + io + io_bytes(&tk.job.p) + held_bytes(c) +
+                                                 growth(sl.ws, need) <=
+                                             c->budget;
+                };
+                bool ok = fits();
+                if (!ok && !trimmed) {
+                    // give back the workspaces of idle slots (this one included) and retry
+                    trimmed = true;
+                    for (Slot& o : c->slots)
+                        if (o.running.empty() && o.ws.held() > 0) o.ws.release();
+                    ok = fits();
+                }
+                if (!ok) {
+                    batch.pop_back();
+                    break;  // FIFO: the next request waits for memory
+                }
+                io += io_bytes(&tk.job.p);
+                ids.push_back(id);
             }
-            if (batch.empty()) break;  // the head does not fit yet
+            if (batch.empty()) {
+                // the head does not fit; with nothing running and nothing left to give back it
+                // never will (the synchronous calls' workspace holds the rest)
+                bool busy = false;
+                for (const Slot& o : c->slots) busy = busy || !o.running.empty();
+                if (!busy) {
+                    const uint64_t id = c->queue.front();
+                    c->queue.pop_front();
+                    Ticket& tk = c->tickets[id];
+                    tk.state = CWO_ERR_NOMEM;
+                    tk.t_done = now_s(c);
+                    if (tk.ready) {
+                        c->ready_pool.push_back(tk.ready);
+                        tk.ready = nullptr;
+                    }
+                    continue;
+                }
+                break;
+            }
+            for (size_t k = 0; k < ids.size(); ++k) c->queue.pop_front();
+            const double t = now_s(c);
+            std::vector<hipEvent_t> waits;
+            for (uint64_t id : ids) {
+                Ticket& tk = c->tickets[id];
+                tk.state = 1;
+                tk.t_start = t;
+                if (tk.ready) waits.push_back(tk.ready);
+            }
+            c->reserved += io;
+            sl.running = ids;  // the slot is busy from here on (drain waits for it)
+            any_running = true;
+            // launch without the queue lock: allocations and launches do not block submit/poll
+            lk.unlock();
             cwo_status st;
             {
                 std::lock_guard<std::mutex> g(c->mu);  // twiddle tables, profiling state
-                st = c->sticky != CWO_OK ? c->sticky
-                                         : run_jobs(c, sl.ws, batch.data(), (int)batch.size(), sl.stream);
+                st = c->sticky;
+                for (hipEvent_t e : waits)
+                    if (st == CWO_OK && hipStreamWaitEvent(sl.stream, e, 0) != hipSuccess)
+                        st = dev_fail(c);
+                if (st == CWO_OK) st = run_jobs(c, sl.ws, batch.data(), (int)batch.size(), sl.stream);
                 if (st == CWO_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = dev_fail(c);
             }
+            lk.lock();
             if (st != CWO_OK) {
+                // nothing of the batch may still run when its tickets report an error
+                (void)hipStreamSynchronize(sl.stream);
                 for (uint64_t id : ids) {
                     Ticket& tk = c->tickets[id];
                     tk.state = st;
                     tk.t_done = now_s(c);
-                    c->reserved -= tk.footprint;
+                    c->reserved -= io_bytes(&tk.job.p);
+                    if (tk.ready) {
+                        c->ready_pool.push_back(tk.ready);
+                        tk.ready = nullptr;
+                    }
                 }
-                continue;
+                sl.running.clear();
             }
-            sl.running = ids;
-            any_running = true;
         }
         c->qcv.notify_all();  // progress for drain()
         if (c->stop && c->queue.empty() && !any_running) break;
@@ -796,14 +959,15 @@ void serve_loop(cwo_ctx* c) {
 cwo_status start_serving(cwo_ctx* c) {
     if (c->worker.joinable()) return CWO_OK;
     if (hipSetDevice(c->device) != hipSuccess) return dev_fail(c);
-    c->slots.resize(kSlots);
     for (Slot& sl : c->slots) {
         // default priority streams
         if (!sl.stream && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             return dev_fail(c);
         if (!sl.done && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             return dev_fail(c);
+        sl.ws.owner = sl.stream;
     }
+    c->slots_ready = true;
     c->stop = false;
     c->worker = std::thread(serve_loop, c);
     return CWO_OK;
@@ -863,11 +1027,11 @@ cwo_status epilogue(cwo_ctx* c, size_t n, bool ok, F&& launch) {
     return CWO_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-cwo_status cwo_submit(cwo_ctx* c, const cwo_job* job, uint64_t* ticket) {
+// after != nullptr: the job's first kernel waits for the work enqueued on that stream
+// before the call (an event recorded there now); the event returns to the pool when the
+// ticket finishes.
+cwo_status submit_impl(cwo_ctx* c, const cwo_job* job, bool ordered, hipStream_t after,
+                       uint64_t* ticket) {
     if (!c || !job || !ticket) return CWO_ERR_INVALID;
     const int kind = job->p.kind;
     cwo_status st = validate(&job->p, kind, true);
@@ -878,15 +1042,47 @@ cwo_status cwo_submit(cwo_ctx* c, const cwo_job* job, uint64_t* ticket) {
     std::lock_guard<std::mutex> lk(c->qmu);
     if (c->sticky != CWO_OK) return c->sticky;
     if (!c->worker.joinable() && (st = start_serving(c)) != CWO_OK) return st;
+    hipEvent_t ready = nullptr;
+    if (ordered) {
+        if (!c->ready_pool.empty()) {
+            ready = c->ready_pool.back();
+            c->ready_pool.pop_back();
+        } else if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) {
+            return dev_fail(c);
+        }
+        if (hipEventRecord(ready, after) != hipSuccess) {
+            c->ready_pool.push_back(ready);
+            return dev_fail(c);
+        }
+    }
     const uint64_t id = c->next_ticket++;
     Ticket tk;
     tk.job = *job;
     tk.footprint = fp;
+    tk.ready = ready;
     tk.t_submit = now_s(c);
     c->tickets.emplace(id, tk);
     c->queue.push_back(id);
     *ticket = id;
     c->qcv.notify_all();
+    return CWO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cwo_status cwo_submit(cwo_ctx* c, const cwo_job* job, uint64_t* ticket) {
+    return submit_impl(c, job, false, nullptr, ticket);
+}
+
+cwo_status cwo_submit_after(cwo_ctx* c, const cwo_job* job, void* hip_stream, uint64_t* ticket) {
+    return submit_impl(c, job, true, (hipStream_t)hip_stream, ticket);
+}
+
+cwo_status cwo_memory_held(cwo_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return CWO_ERR_INVALID;
+    *bytes = held_bytes(c);
     return CWO_OK;
 }
 
@@ -966,6 +1162,9 @@ cwo_status cwo_destroy(cwo_ctx* c) {
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
         for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c->ready_pool) (void)hipEventDestroy(e);
+        for (auto& kv : c->tickets)
+            if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
     }
     delete c;
     return CWO_OK;

@@ -163,6 +163,9 @@ SIGNATURES = {
                                 ctypes.c_void_p]),
     "cwo_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job),
                                     ctypes.POINTER(ctypes.c_uint64)]),
+    "cwo_submit_after": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "cwo_memory_held": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "cwo_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "cwo_ticket_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64,
                                          ctypes.POINTER(TicketInfo)]),
@@ -532,8 +535,11 @@ class Context:
 
     # -- serving --------------------------------------------------------------
     def submit(self, kind, u, out, dx=10e-6, dy=None, wavelength=633e-9, z=0.1,
-               precision="f32"):
-        """Queue one propagation; returns a ticket. u and out must stay alive until done."""
+               precision="f32", stream=None):
+        """Queue one propagation; returns a ticket. u and out must stay alive (and out
+        untouched) until done. The job waits for the work already enqueued on `stream`
+        (torch's current stream of u's device by default), so u may come straight from
+        asynchronous kernels."""
         u = self._field(u)
         out = self._field(out)
         ny, nx = u.shape
@@ -543,10 +549,19 @@ class Context:
         job.inp = u.data_ptr()
         job.out = out.data_ptr()
         t = ctypes.c_uint64()
-        st = self._lib.cwo_submit(self.handle, ctypes.byref(job), ctypes.byref(t))
+        st = self._lib.cwo_submit_after(self.handle, ctypes.byref(job), self._stream(u, stream),
+                                        ctypes.byref(t))
         if st != CWO_OK:
-            raise CwoError(st, "cwo_submit")
+            raise CwoError(st, "cwo_submit_after")
         return t.value
+
+    def memory_held(self):
+        """Bytes of device memory the context holds (tables, workspaces, serving slots)."""
+        b = ctypes.c_size_t()
+        st = self._lib.cwo_memory_held(self.handle, ctypes.byref(b))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_memory_held")
+        return b.value
 
     def poll(self, ticket):
         state = ctypes.c_int32()

@@ -75,6 +75,121 @@ def test_alone_vs_mix(torch):
         alone.close()
 
 
+def test_alone_vs_mix_serving_sizes(torch):
+    """The serving workload's sizes (512^2 ... 4096^2), each request with its own seeded field
+    (seed 5000 + i), ASM and Fresnel, random z and wavelength, plus an FP16-storage pair on
+    one field (16-bit requests never form a z-stack, so each must equal its own call)."""
+    from paper_1107_5578_amd import cwo
+    reqs = W.serving_requests(16, 1.0, seed=5, sizes=(512, 1024, 2048, 4096))
+    sizes = (512, 1024, 2048, 4096)
+    server = cwo.Context(0, hbm_budget_bytes=6 << 30)
+    alone = cwo.Context(0)
+    try:
+        jobs = []
+        for i, r in enumerate(reqs):
+            # the request mix's kinds, distances and wavelengths, every size four times
+            n = sizes[i % 4]
+            u = torch.from_numpy(W.uniform_random_field(n, 5000 + i)).cuda()
+            jobs.append((r.kind, u, dict(dx=r.pitch, wavelength=r.wavelength, z=r.z), "f32"))
+        u16 = torch.from_numpy(W.uniform_random_field(1024, 4999)).cuda()
+        for z in (0.3, 0.5):
+            jobs.append(("asm", u16, dict(dx=8e-6, wavelength=532e-9, z=z), "f16"))
+        outs = [torch.empty_like(u) for _, u, _, _ in jobs]
+        note("serving %d requests of sizes %s" % (len(jobs), sizes))
+        tickets = [server.submit(k, u, o, precision=pr, **kw)
+                   for (k, u, kw, pr), o in zip(jobs, outs)]
+        server.drain()
+        checked = set()
+        for t, (kind, u, kw, pr), o in zip(tickets, jobs, outs):
+            assert server.poll(t) == cwo.DONE
+            fn = alone.asm if kind == "asm" else alone.fresnel
+            ref = fn(u, kw["dx"], kw["dx"], kw["wavelength"], kw["z"], precision=pr)
+            torch.cuda.synchronize()
+            err = D.rel_l2(o.cpu().numpy(), ref.cpu().numpy().astype(np.complex128))
+            assert err <= 1e-6, (u.shape, kind, pr, err)
+            n = u.shape[0]
+            if pr == "f32" and n not in checked:
+                # one request per size against the FP64 oracle
+                note("oracle check %s %d^2" % (kind, n))
+                ora = D.propagate(u.cpu().numpy(), D.ASM if kind == "asm" else D.FRESNEL,
+                                  kw["dx"], kw["dx"], kw["wavelength"], kw["z"])
+                e2 = D.rel_l2(o.cpu().numpy(), ora)
+                note("  rel_l2 = %.3e" % e2)
+                assert e2 <= 1e-5
+                checked.add(n)
+        assert checked == {512, 1024, 2048, 4096}
+        assert server.memory_held() <= 6 << 30
+    finally:
+        server.close()
+        alone.close()
+
+
+def test_memory_held_within_budget(torch):
+    """Held device memory never exceeds the budget: 4096^2 requests (each 512 MiB of fields
+    and scratch) and then 512^2 requests through a 1.25 GiB budget; idle slots give their
+    4096^2 scratch back when memory is short."""
+    from paper_1107_5578_amd import cwo
+    budget = 1280 << 20
+    server = cwo.Context(0, hbm_budget_bytes=budget)
+    try:
+        big = torch.from_numpy(W.uniform_random_field(4096, 61)).cuda()
+        small = torch.from_numpy(W.uniform_random_field(512, 62)).cuda()
+        outs_b = [torch.empty_like(big) for _ in range(3)]
+        outs_s = [torch.empty_like(small) for _ in range(24)]
+        tickets = [server.submit("asm", big, o, dx=8e-6, wavelength=532e-9, z=0.2 + 0.1 * i)
+                   for i, o in enumerate(outs_b)]
+        tickets += [server.submit("fresnel" if i % 2 else "asm", small, o, dx=8e-6,
+                                  wavelength=633e-9, z=0.05 + 0.01 * i)
+                    for i, o in enumerate(outs_s)]
+        peak = 0
+        deadline = time.time() + 120
+        while time.time() < deadline:
+            peak = max(peak, server.memory_held())
+            if all(server.poll(t) >= cwo.DONE or server.poll(t) < 0 for t in tickets):
+                break
+            time.sleep(0.0005)
+        server.drain()
+        peak = max(peak, server.memory_held())
+        note("peak held %.1f MiB of a %.1f MiB budget" % (peak / 2**20, budget / 2**20))
+        assert all(server.poll(t) == cwo.DONE for t in tickets)
+        assert peak <= budget
+        # results are right after the slots traded their scratch
+        ref = D.asm(small.cpu().numpy(), 8e-6, 8e-6, 633e-9, 0.05 + 0.01 * 22)
+        assert D.rel_l2(outs_s[22].cpu().numpy(), ref) <= 1e-5
+    finally:
+        server.close()
+
+
+def test_submit_orders_after_producer_stream(torch):
+    """A field written by asynchronous kernels on the caller's stream just before submit is
+    read only after they finish (cwo_submit_after, what Context.submit uses)."""
+    from paper_1107_5578_amd import cwo
+    server = cwo.Context(0)
+    alone = cwo.Context(0)
+    try:
+        n = 1024
+        base = torch.from_numpy(W.uniform_random_field(n, 71)).cuda()
+        torch.cuda.synchronize()
+        outs, fields = [], []
+        for k in range(6):
+            # a long chain of elementwise kernels on the current stream, then submit at once
+            u = base.clone()
+            for _ in range(40):
+                u = u * torch.exp(torch.tensor(0.05j, dtype=torch.complex64, device="cuda"))
+            fields.append(u)
+            o = torch.empty_like(u)
+            outs.append(o)
+            server.submit("asm", u, o, dx=8e-6, wavelength=532e-9, z=0.1 + 0.05 * k)
+        server.drain()
+        for k, (u, o) in enumerate(zip(fields, outs)):
+            ref = alone.asm(u, 8e-6, 8e-6, 532e-9, 0.1 + 0.05 * k)
+            torch.cuda.synchronize()
+            assert D.rel_l2(o.cpu().numpy(), ref.cpu().numpy().astype(np.complex128)) <= 1e-6
+    finally:
+        server.close()
+        alone.close()
+
+
 def test_admission_by_memory(torch):
     from paper_1107_5578_amd import cwo
     n = 512
