@@ -129,6 +129,20 @@ cwo_status cwo_destroy(cwo_ctx* ctx);
  * in, out: device complex64 [ny][nx]. Scratch: ny * 2nx complex64 held by the context. */
 cwo_status cwo_asm(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out, void* hip_stream);
 
+/* cwo_asm for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same parameters, layout, result
+ * (the same kernels, bit for bit) and stream ordering as cwo_asm, but it allocates nothing:
+ * its twiddle tables and padded plane live in one statically allocated device array of
+ * 64 MiB + 128 KiB that every device the library runs on holds until the process ends.
+ * Limits: complex64 storage only (other precisions: CWO_ERR_UNSUPPORTED); the padded plane
+ * ny * 2nx complex64 (ny * nx with CWO_FLAG_NOPAD) must fit 64 MiB, i.e. fields up to
+ * 2048 x 2048 (larger: CWO_ERR_NOMEM, before any launch). Every call on a device shares that
+ * device's array and leaves its contents behind, so calls that overlap on one device (on
+ * different streams or from different threads without ordering) race and give wrong
+ * results; order them on one stream. */
+cwo_status cwo_asm_noalloc(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,
+                           void* hip_stream);
+
 /* Fresnel diffraction, convolution form (Sec. 2.1.1, Eq. fre_conv_fft), same layout as
  * cwo_asm. The two 1-D factors of FFT[h_F] are cached per parameter set. */
 cwo_status cwo_fresnel(cwo_ctx* ctx, const cwo_params* p, const void* in, void* out,

@@ -1027,6 +1027,42 @@ cwo_status epilogue(cwo_ctx* c, size_t n, bool ok, F&& launch) {
     return CWO_OK;
 }
 
+// ---- scratch of the no-allocation entry point ------------------------------------------
+// cwo_asm_noalloc keeps its twiddle tables and its padded plane in one statically
+// allocated device array instead of memory it would have to allocate: up to 2 * 8192
+// twiddles, then a plane of at most 64 MiB (ny * 2nx complex64, i.e. fields up to
+// 2048 x 2048). Every device the library runs on holds its own copy until the process ends.
+constexpr size_t kStaticTwiddleBytes = 2 * sizeof(float2) * 8192;
+constexpr size_t kStaticPlaneBytes = size_t(64) << 20;
+constexpr size_t kStaticScratchBytes = kStaticTwiddleBytes + kStaticPlaneBytes;
+constexpr int kMaxDevices = 64;
+
+// On the host this name stands for the array, not for its device address: kernels and
+// copies take the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+void* g_static_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device; looked up
+// once per device (cwo_create does it), then reused.
+void* static_scratch(int device, cwo_status* st) {
+    if (device < 0 || device >= kMaxDevices) {
+        *st = CWO_ERR_UNSUPPORTED;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (!g_static_addr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            *st = CWO_ERR_DEVICE;
+            return nullptr;
+        }
+        g_static_addr[device] = ptr;
+    }
+    return g_static_addr[device];
+}
+
 // after != nullptr: the job's first kernel waits for the work enqueued on that stream
 // before the call (an event recorded there now); the event returns to the pool when the
 // ticket finishes.
@@ -1138,6 +1174,8 @@ cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes) {
     if (hipGetDeviceCount(&n) != hipSuccess) return CWO_ERR_DEVICE;
     if (device < 0 || device >= n) return CWO_ERR_INVALID;
     if (hipSetDevice(device) != hipSuccess) return CWO_ERR_DEVICE;
+    cwo_status st = CWO_OK;
+    if (device < kMaxDevices && !static_scratch(device, &st)) return st;
     cwo_ctx* c = new cwo_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
@@ -1172,6 +1210,36 @@ cwo_status cwo_destroy(cwo_ctx* c) {
 
 cwo_status cwo_asm(cwo_ctx* c, const cwo_params* p, const void* in, void* out, void* stream) {
     return propagate(c, p, CWO_ANGULAR, in, out, stream);
+}
+
+cwo_status cwo_asm_noalloc(cwo_ctx* c, const cwo_params* p, const void* in, void* out,
+                           void* stream) {
+    if (!c) return CWO_ERR_INVALID;
+    cwo_status st = validate(p, CWO_ANGULAR, false);  // complex64 storage only
+    if (st != CWO_OK) return st;
+    if (!in || !out) return CWO_ERR_INVALID;
+    const Geometry g = geometry(p);
+    if (sizeof(float2) * (size_t)g.ny * g.mx > kStaticPlaneBytes) return CWO_ERR_NOMEM;
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = begin(c);
+    if (st != CWO_OK) return st;
+    unsigned char* base = (unsigned char*)static_scratch(c->device, &st);
+    if (!base) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // twiddles are regenerated on the caller's stream each call (the array keeps whatever
+    // the last call on this device left there)
+    float2* twx = (float2*)base;
+    float2* twy = twx + g.mx;
+    void* buf = base + kStaticTwiddleBytes;
+    CWO_HIP(c, cwo::launch_twiddles(twx, g.mx, s));
+    CWO_HIP(c, cwo::launch_twiddles(twy, g.my, s));
+    cwo::Storage sto;
+    sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
+    const cwo::AsmScalars a = asm_scalars(p, g, p->z);
+    CWO_HIP(c, cwo::launch_row_fwd((const float2*)in, buf, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s));
+    CWO_HIP(c, cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, sto, twy, s));
+    CWO_HIP(c, cwo::launch_row_inv(buf, (float2*)out, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s));
+    return CWO_OK;
 }
 
 cwo_status cwo_fresnel(cwo_ctx* c, const cwo_params* p, const void* in, void* out, void* stream) {

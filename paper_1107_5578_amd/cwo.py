@@ -119,6 +119,8 @@ SIGNATURES = {
                                  ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_fresnel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "cwo_asm_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cwo_asm_shifted": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                          ctypes.POINTER(Shift), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
@@ -297,6 +299,14 @@ class Context:
         """Angular spectrum propagation by z (stream-ordered; returns the output tensor)."""
         return self._propagate(self._lib.cwo_asm, ANGULAR, u, dx, dy, wavelength, z, precision,
                                nopad, out, stream)
+
+    def asm_noalloc(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, nopad=False,
+                    out=None, stream=None):
+        """cwo_asm through the entry point that allocates no device memory (its scratch is a
+        static device array; calls that overlap on one device race). Pass `out` to keep the
+        call free of allocations on the Python side too."""
+        return self._propagate(self._lib.cwo_asm_noalloc, ANGULAR, u, dx, dy, wavelength, z,
+                               "f32", nopad, out, stream)
 
     def fresnel(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, precision="f32",
                 nopad=False, out=None, stream=None, fresnel_tf=False):
