@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -38,7 +40,8 @@ def stage_bytes(n: int, elem: int = 8) -> dict:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_1107_5578_amd/csrc/plane.hip", "paper_1107_5578_amd/csrc/column.hpp",
+    for rel in ("paper_1107_5578_amd/csrc/plane.hip", "paper_1107_5578_amd/csrc/column.hip",
+                "paper_1107_5578_amd/csrc/column.hpp",
                 "paper_1107_5578_amd/csrc/kernel_common.hpp",
                 "paper_1107_5578_amd/csrc/fft_device.hpp", "paper_1107_5578_amd/csrc/launch.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
@@ -59,23 +62,46 @@ def committed_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(u_np, cfg, kind="asm", min_seconds: float = 10.0, max_planes: int = 30):
-    """The FP64 oracle on the host cores, on whole planes of the same workload."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(u_np, cfg, kind="asm", min_seconds: float = 10.0, max_planes: int = 30,
+                 single_seconds: float = 8.0):
+    """The FP64 oracle on the host cores, on whole planes of the same workload: first with
+    every OpenMP thread, then (a shorter sample) with one thread."""
     from oracle import _native, diffraction as D
     threads = _native.max_threads()
-    t0 = time.perf_counter()
-    ref = None
-    done = 0
-    for _ in range(max_planes):
-        ref = D.propagate(u_np, kind, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
-        done += 1
-        if time.perf_counter() - t0 > min_seconds:
-            break
-    dt = time.perf_counter() - t0
+
+    def sample(limit_s, max_n):
+        t0 = time.perf_counter()
+        ref, done = None, 0
+        for _ in range(max_n):
+            ref = D.propagate(u_np, kind, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+            done += 1
+            if time.perf_counter() - t0 > limit_s:
+                break
+        return ref, done, time.perf_counter() - t0
+
+    ref, done, dt = sample(min_seconds, max_planes)
+    # one OpenMP thread from here on (the oracle keeps the setting of its last call)
+    _native.fft2(np.zeros((16, 16), dtype=np.complex128), threads=1)
+    _, done1, dt1 = sample(single_seconds, 4)
+    _native.fft2(np.zeros((16, 16), dtype=np.complex128), threads=threads)
     return ref, {"value": done / dt, "unit": "planes/s", "cores": threads, "kind": "oracle",
+                 "cpu_model": host_cpu_model(),
                  "sample": "%d whole %dx%d %s plane(s) of the timed workload, FP64, "
                            "%d OpenMP threads for the FFTs (%.1f s)"
-                           % (done, u_np.shape[1], u_np.shape[0], kind, threads, dt)}
+                           % (done, u_np.shape[1], u_np.shape[0], kind, threads, dt),
+                 "single_thread": {"value": done1 / dt1, "unit": "planes/s",
+                                   "sample": "%d whole plane(s), 1 thread (%.1f s)" % (done1, dt1)}}
 
 
 def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm):
@@ -221,15 +247,23 @@ def rel_l2(y, ref):
 def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 0.95)):
     """Serving: a stream of mixed requests (sizes 512..4096^2, ASM/Fresnel 50/50,
     z ~ U[0.01, 1] m, wavelength in {473, 532, 633} nm, 8 um pitch) through cwo_submit /
-    cwo_poll under an HBM budget. Field content does not change the work, so each size uses
-    one seeded field; outputs rotate through a ring per size (a buffer is reused only after
-    its previous request is done)."""
-    import numpy as np
+    cwo_poll under an HBM budget. Every request reads a field of its own: 10k distinct
+    fields do not fit, so each size has a ring of FIELD_RING distinct seeded fields and
+    successive requests of one size take successive fields (no two neighbouring requests
+    share an input, so none of them can be merged into a z-stack). Outputs rotate through a
+    ring per size (a buffer is reused only after its previous request is done)."""
+    FIELD_RING = 4
     reqs = W.serving_requests(count, 1.0, seed=5)
     sizes = sorted({r.n for r in reqs})
-    fields = {n: torch.from_numpy(W.uniform_random_field(n, 5000 + n)).to(dev) for n in sizes}
+    fields = {n: [torch.from_numpy(W.uniform_random_field(n, 5000 + FIELD_RING * k + i)).to(dev)
+                  for i in range(FIELD_RING)] for k, n in enumerate(sizes)}
+    seq = {n: 0 for n in sizes}
+    req_field = []
+    for r in reqs:
+        req_field.append(fields[r.n][seq[r.n] % FIELD_RING])
+        seq[r.n] += 1
     ring = 40
-    outs = {n: [torch.empty_like(fields[n]) for _ in range(ring)] for n in sizes}
+    outs = {n: [torch.empty_like(fields[n][0]) for _ in range(ring)] for n in sizes}
 
     def run(arrivals):
         srv = ctx_cls(0, hbm_budget_bytes=budget)
@@ -237,7 +271,7 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
         used = {n: 0 for n in sizes}
         tickets = []
         t0 = time.perf_counter()
-        for r, ta in zip(reqs, arrivals):
+        for r, f, ta in zip(reqs, req_field, arrivals):
             if ta is not None:
                 while time.perf_counter() - t0 < ta:
                     pass
@@ -246,8 +280,7 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
             prev = owner[r.n][k]
             while prev is not None and srv.poll(prev) < 2:
                 time.sleep(0.0001)
-            t = srv.submit(r.kind, fields[r.n], outs[r.n][k], dx=r.pitch, wavelength=r.wavelength,
-                           z=r.z)
+            t = srv.submit(r.kind, f, outs[r.n][k], dx=r.pitch, wavelength=r.wavelength, z=r.z)
             owner[r.n][k] = t
             tickets.append(t)
         srv.drain()
@@ -263,14 +296,14 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
     # plain per-call form on one stream, same requests in order (first 2000)
     plain_ctx = ctx_cls(0)
     nplain = min(2000, count)
-    for r in reqs[:8]:
+    for r, f in zip(reqs[:8], req_field):
         (plain_ctx.asm if r.kind == "asm" else plain_ctx.fresnel)(
-            fields[r.n], r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
+            f, r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for r in reqs[:nplain]:
+    for r, f in zip(reqs[:nplain], req_field):
         (plain_ctx.asm if r.kind == "asm" else plain_ctx.fresnel)(
-            fields[r.n], r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
+            f, r.pitch, r.pitch, r.wavelength, r.z, out=outs[r.n][0])
     torch.cuda.synchronize()
     plain_rps = nplain / (time.perf_counter() - t0)
     plain_ctx.close()
@@ -278,8 +311,10 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
     closed = run([None] * count)
     cap = closed["req_per_s"]
     out = {"workload": "%d requests, sizes %s^2 uniform, ASM/Fresnel 50/50, z~U[0.01,1] m, "
-                       "lambda in {473,532,633} nm, 8 um, HBM budget %d GiB"
-                       % (count, "/".join(str(n) for n in sizes), budget >> 30),
+                       "lambda in {473,532,633} nm, 8 um, HBM budget %d GiB, a ring of %d "
+                       "distinct fields per size (no two successive requests of a size share "
+                       "an input)" % (count, "/".join(str(n) for n in sizes), budget >> 30,
+                                      FIELD_RING),
            "plain_per_call_req_per_s": round(plain_rps, 1),
            "closed_loop": closed, "served_vs_plain": round(cap / plain_rps, 3), "open_loop": {}}
     for f in rates:
@@ -410,7 +445,7 @@ def main():
         # batched form: the same field to 64 distances in one cwo_zstack call, against the
         # same 64 distances as 64 plain calls (the plain figure above is one distance)
         zs = list(W.zstack_distances(64, 0.05, 0.5))
-        z_form, z_chunk, _ = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+        z_form, z_chunk, _, _ = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
         z_pps, z_ms = time_zstack(ctx, torch, u, zs, cfg.pitch, cfg.wavelength, 5, 2)
         batched = {"form": "cwo_zstack, one %dx%d field to 64 distances in [0.05, 0.5] m" % (n, n),
                    "planes_per_s": round(z_pps, 1), "ms_per_stack": round(z_ms, 4),
@@ -420,32 +455,37 @@ def main():
         u3 = torch.from_numpy(W.field_for(c3)).to(dev)
         z3 = list(W.zstack_distances(64, 0.05, 0.2))
         # the library's autotuner picks the row-pass form and the chunk size for this stack
-        form, zchunk, _ = ctx.autotune(u3, 64, c3.pitch, c3.pitch, c3.wavelength, 0.1)
+        form, zchunk, _, _ = ctx.autotune(u3, 64, c3.pitch, c3.pitch, c3.wavelength, 0.1)
         c3_pps, c3_ms = time_zstack(ctx, torch, u3, z3, c3.pitch, c3.wavelength, 10, 2)
         batched["zstack_1024x64"] = {"planes_per_s": round(c3_pps, 1), "ms_per_stack": round(c3_ms, 4),
                                      "schedule": {"row_form": form, "zchunk": zchunk},
                                      "workload": "1024x1024 speckle, 4um, 633nm, 64 z in [0.05, 0.2] m"}
         del u3
-        # 64 independent fields at one distance: one cwo_batch (one launch per pass) vs the
-        # same 64 propagations as plain calls
+        # 64 independent fields, each at its own distance (and every third one Fresnel): one
+        # cwo_batch (one launch per pass, a transfer function per plane) vs the same 64
+        # propagations as plain calls
         batched["independent_fields"] = {}
+        zk = [float(z) for z in W.zstack_distances(64, 0.05, 0.5)]
+        kinds = ["fresnel" if k % 3 == 1 else "asm" for k in range(64)]
         for ni in (n, 512):
             fields = [torch.from_numpy(W.uniform_random_field(ni, 800 + k)).to(dev) for k in range(64)]
             outs = [torch.empty_like(f) for f in fields]
-            kw = dict(dx=cfg.pitch, dy=cfg.pitch, wavelength=cfg.wavelength, z=cfg.z)
-            jobs = [("asm", f, o, kw) for f, o in zip(fields, outs)]
+            jobs = [(kd, f, o, dict(dx=cfg.pitch, dy=cfg.pitch, wavelength=cfg.wavelength, z=z))
+                    for kd, f, o, z in zip(kinds, fields, outs, zk)]
             b_ms = time_call(torch, stream, lambda: ctx.batch(jobs), 5, 2)
 
             def plain():
-                for f, o in zip(fields, outs):
-                    ctx.asm(f, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z, out=o)
+                for kd, f, o, z in zip(kinds, fields, outs, zk):
+                    (ctx.asm if kd == "asm" else ctx.fresnel)(f, cfg.pitch, cfg.pitch,
+                                                               cfg.wavelength, z, out=o)
 
             p_ms = time_call(torch, stream, plain, 5, 2)
             batched["independent_fields"]["%d" % ni] = {
                 "planes_per_s": round(64 * 1000.0 / b_ms, 1),
                 "plain_planes_per_s": round(64 * 1000.0 / p_ms, 1),
                 "vs_plain": round(p_ms / b_ms, 3),
-                "workload": "64 independent %dx%d uniform random fields, one z" % (ni, ni)}
+                "workload": "64 independent %dx%d uniform random fields, 64 distances in "
+                            "[0.05, 0.5] m, ASM with every third plane Fresnel" % (ni, ni)}
             del fields, outs
         # the same work captured once into a HIP graph and replayed (launch overhead and
         # host work paid once): the 1024^2 x 64 z-stack, 64 independent 512^2 fields in one

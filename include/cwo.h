@@ -239,21 +239,39 @@ cwo_status cwo_band_limit(const cwo_params* p, cwo_shift* shift);
 
 /* Schedule of one parameter set, as picked by cwo_autotune. */
 typedef struct {
-    int32_t row_form;     /* row passes: 1 a resident grid that prefetches the next rows,
-                             2 one row group per block, 0 the default choice */
+    int32_t row_form;     /* row passes on the row-major plane: 1 a resident grid that
+                             prefetches the next rows, 2 one row group per block, 0 the
+                             default choice */
     int32_t zchunk;       /* planes per z-stack launch (0: single-plane calls) */
     float us_per_plane;   /* the best measured time */
+    int32_t layout;       /* padded plane between the passes: 1 row-major, 2 tiled (four
+                             columns per tile, two rows per row-pass group), 0 the default
+                             choice (tiled for 2048 <= 2nx <= 4096) */
 } cwo_tuning;
 
-/* Autotuner: runs the candidate schedules of this parameter set (row-pass form, and for
- * nz > 1 the z-stack chunk size) on the given buffers, times each on the stream with HIP
- * events (the call synchronises the stream), and keeps the fastest in the context for
- * (kind, nx, ny, precision, flags, nz); later cwo_asm / cwo_fresnel calls (nz = 1) and
- * z-stacks of nz planes with those parameters use it. Results do not depend on the
- * schedule. in: complex64 [ny][nx]; out: complex64 [nz][ny][nx], overwritten; p->z is used
- * for every plane. best may be null. Not thread-safe with other calls on the context. */
+/* Autotuner: runs the candidate schedules of this parameter set (for single planes the
+ * plane layout, row-major or tiled where the plane is padded and 2048 <= 2nx <= 8192, and
+ * the row-pass form of the row-major plane; for nz > 1 the row-pass form and the z-stack
+ * chunk size) on the given buffers, times each on the stream with HIP events (the call
+ * synchronises the stream), and keeps the fastest in the context for (kind, nx, ny,
+ * precision, flags, nz); later cwo_asm / cwo_fresnel calls (nz = 1) and z-stacks of nz
+ * planes with those parameters use it. Results do not depend on the schedule. in:
+ * complex64 [ny][nx]; out: complex64 [nz][ny][nx], overwritten; p->z is used for every
+ * plane. best may be null. Not thread-safe with other calls on the context.
+ * Tune cache: if the environment variable CWO_TUNE_CACHE names a file, cwo_create loads the
+ * schedules stored there and each successful cwo_autotune rewrites it with every schedule
+ * the context holds (JSON: an array of flat objects, one per line, with the key fields
+ * kind, nx, ny, precision, flags, nz and the cwo_tuning fields). An unreadable or missing
+ * file is ignored. */
 cwo_status cwo_autotune(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const void* in, void* out,
                         void* hip_stream, cwo_tuning* best);
+
+/* Install a schedule for (kind, nx, ny, precision, flags, nz) without timing anything (one
+ * chosen elsewhere, e.g. read from a tune cache); a null t removes the context's schedule
+ * so the defaults apply again. CWO_ERR_INVALID for out-of-range fields (row_form 0..2,
+ * zchunk 0..64, layout 0..2), CWO_ERR_UNSUPPORTED for a tiled layout the geometry cannot
+ * take. Host only; results never depend on the schedule. */
+cwo_status cwo_set_tuning(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const cwo_tuning* t);
 
 /* z-stack: one field propagated to nz distances, the paper's 3-D field built by stacking
  * 2-D propagations (Sec. 2.3, Diffract3D). p->kind selects CWO_ANGULAR or

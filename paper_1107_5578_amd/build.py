@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcwo.so")
-SOURCES = ["plane.hip", "shifted.hip", "fourier.hip", "sfresnel.hip", "zstack.hip", "gs.hip",
+SOURCES = ["plane.hip", "column.hip", "shifted.hip", "fourier.hip", "sfresnel.hip", "zstack.hip", "gs.hip",
            "tables.hip", "epilogue.hip", "pls.hip", "cwo.cpp"]
 ARCH = "gfx950"
 

@@ -123,6 +123,39 @@ struct FresnelH {
     }
 };
 
+// ---- per-plane transfer functions of a mixed batch -------------------------------------
+//
+// Planes of one geometry (sizes, pitch, flags) whose distance, wavelength or kind differ
+// share the row passes; their column pass runs as one launch per transfer-function form
+// present (fast ASM with the series to s^4, to s^9, Fresnel factors), each over its planes
+// listed by buffer index, and each plane gets exactly the transfer function its single call
+// would use. The kernel of each form is the single-plane kernel of that form.
+template <class HF>
+struct PlaneList {
+    int n;
+    int idx[kZChunk];  // buffer plane of launch plane k
+    HF f[kZChunk];     // its transfer function
+};
+
+// Transfer function and buffer plane of launch plane pl: the functor itself and pl, or the
+// list's entries.
+template <class HF>
+__device__ __forceinline__ const HF& plane_tf(const HF& hf, int) {
+    return hf;
+}
+template <class HF>
+__device__ __forceinline__ const HF& plane_tf(const PlaneList<HF>& t, int pl) {
+    return t.f[pl];
+}
+template <class HF>
+__device__ __forceinline__ int buffer_plane(const HF&, int pl) {
+    return pl;
+}
+template <class HF>
+__device__ __forceinline__ int buffer_plane(const PlaneList<HF>& t, int pl) {
+    return t.idx[pl];
+}
+
 // Transfer functions whose per-row factors are memory reads say so with kRowsEarly.
 template <class HF>
 constexpr bool rows_early() {
@@ -131,12 +164,16 @@ constexpr bool rows_early() {
 }
 
 // Column pass: forward FFT of COLS columns, multiplication by the transfer function,
-// inverse FFT, in place; one (plane, column tile) item per block.
-template <int M, bool HALF, class HF, class ST>
+// inverse FFT, in place; one (plane, column tile) item per block. LAY addresses the
+// plane (row-major or tiled). With HALF the rows Ny..My-1 of the padded column are zero:
+// they are neither loaded nor added in the first forward pass, and only rows < Ny of the
+// result are computed to the end and stored.
+template <int M, bool HALF, class HF, class ST, class LAY>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_col(typename ST::E* __restrict__ buf,
                                                               int ny, int mx, int batch,
                                                               size_t plane, HF hf, float hscale,
-                                                              const float2* __restrict__ tw) {
+                                                              const float2* __restrict__ tw,
+                                                              LAY lay) {
     using C = ColCfg<M>;
     constexpr int E = C::E, T = C::T, P = C::P;
     using SE = typename ST::E;
@@ -154,14 +191,16 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     const int col0 = (tile * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
     const bool active = col0 < mx;                  // tiles may overhang narrow planes
     const int col = active ? col0 : 0;
-    SE* base = buf + pl * plane + col;
+    SE* base = buf + buffer_plane(hf, pl) * plane;
+    const auto& hfp = plane_tf(hf, pl);  // this block's transfer function
+    using PH = std::decay_t<decltype(hfp)>;
     float2 v[P][E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
         const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
         if (ld) {
-            const PK t = *reinterpret_cast<const PK*>(base + (size_t)y * mx);
+            const PK t = *reinterpret_cast<const PK*>(base + lay.at(y, col));
 #pragma unroll
             for (int p = 0; p < P; ++p) v[p][r] = ST::dec(t.e[p]);
         } else {
@@ -169,25 +208,26 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
             for (int p = 0; p < P; ++p) v[p][r] = make_float2(0.f, 0.f);
         }
     }
-    typename HF::Col hc[P];
+    typename PH::Col hc[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) hc[p] = hf.column(col + p);
+    for (int p = 0; p < P; ++p) hc[p] = hfp.column(col + p);
     // (at M = 8192 the extra registers cost more than the hidden latency: measured)
-    constexpr bool EARLY = rows_early<HF>() && M <= 4096;
-    typename HF::Row hre[EARLY ? E : 1];
+    constexpr bool EARLY = rows_early<PH>() && M <= 4096;
+    typename PH::Row hre[EARLY ? E : 1];
     if constexpr (EARLY) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) hre[r] = hf.row(j + r * T);
+        for (int r = 0; r < E; ++r) hre[r] = hfp.row(j + r * T);
     }
-    fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
+    if constexpr (HALF) fft_zpad<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
+    else fft<M, E, P, FWD, C::SPLIT>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        typename HF::Row hr;
+        typename PH::Row hr;
         if constexpr (EARLY) hr = hre[r];
-        else hr = hf.row(j + r * T);
+        else hr = hfp.row(j + r * T);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            float2 h = hf(hc[p], hr);
+            float2 h = hfp(hc[p], hr);
             if (hscale != 1.0f) h = make_float2(h.x * hscale, h.y * hscale);
             v[p][r] = cmul(v[p][r], h);
         }
@@ -201,7 +241,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
             PK t;
 #pragma unroll
             for (int p = 0; p < P; ++p) t.e[p] = ST::enc(v[p][r]);
-            *reinterpret_cast<PK*>(base + (size_t)y * mx) = t;
+            *reinterpret_cast<PK*>(base + lay.at(y, col)) = t;
         }
     }
 }

@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <chrono>
 #include <atomic>
 #include <condition_variable>
@@ -429,17 +432,89 @@ TuneKey tune_key(const cwo_params* p, int kind, int nz) {
     return TuneKey{kind, p->nx, p->ny, p->precision, (int)p->flags, nz};
 }
 
-// The tuned schedule of a parameter set ({0, 0, 0}: none, the defaults apply).
+// The tuned schedule of a parameter set (all zero: none, the defaults apply).
 cwo_tuning tuned_for(cwo_ctx* c, const cwo_params* p, int kind, int nz) {
     std::lock_guard<std::mutex> g(c->tmu);
     auto it = c->tuned.find(tune_key(p, kind, nz));
-    return it == c->tuned.end() ? cwo_tuning{0, 0, 0.0f} : it->second;
+    return it == c->tuned.end() ? cwo_tuning{0, 0, 0.0f, 0} : it->second;
+}
+
+// Whether the tiled plane can be used for this geometry at all (padded planes of
+// 2048 <= Mx <= 8192; the default rule takes it up to 4096).
+bool tiles_possible(const Geometry& g) {
+    return g.mx == 2 * g.nx && g.my == 2 * g.ny && g.mx >= 2048 && g.mx <= 8192;
+}
+
+// Plane layout of a single propagation: the tuned one if any (1 row-major, 2 tiled), else
+// the default rule.
+int plane_layout(const Geometry& g, const cwo_tuning& t) {
+    if (t.layout == 1) return 0;
+    if (t.layout == 2 && tiles_possible(g)) return 1;
+    return cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
 }
 
 void set_tuned(cwo_ctx* c, const TuneKey& k, const cwo_tuning* t) {
     std::lock_guard<std::mutex> g(c->tmu);
     if (t) c->tuned[k] = *t;
     else c->tuned.erase(k);
+}
+
+// ---- tune cache ----------------------------------------------------------------------
+//
+// With CWO_TUNE_CACHE naming a file, cwo_create reads the schedules stored there and every
+// successful cwo_autotune rewrites the file with all schedules the context knows: a JSON
+// array of flat objects, one per line, e.g.
+//   {"kind": 1, "nx": 2048, "ny": 2048, "precision": 0, "flags": 0, "nz": 1,
+//    "row_form": 1, "zchunk": 0, "layout": 2, "us_per_plane": 126.5}
+// (written on one line). Lines that do not parse are ignored; a missing file is no error.
+const char* tune_cache_path() {
+    const char* p = std::getenv("CWO_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void load_tune_cache(cwo_ctx* c) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        TuneKey k{};
+        cwo_tuning t{};
+        const int n = std::sscanf(line,
+                                  " {\"kind\": %d, \"nx\": %d, \"ny\": %d, \"precision\": %d, "
+                                  "\"flags\": %d, \"nz\": %d, \"row_form\": %d, \"zchunk\": %d, "
+                                  "\"layout\": %d, \"us_per_plane\": %f",
+                                  &k.kind, &k.nx, &k.ny, &k.precision, &k.flags, &k.nz, &t.row_form,
+                                  &t.zchunk, &t.layout, &t.us_per_plane);
+        if (n == 10) set_tuned(c, k, &t);
+    }
+    std::fclose(f);
+}
+
+void save_tune_cache(cwo_ctx* c) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::lock_guard<std::mutex> g(c->tmu);
+    std::fprintf(f, "[\n");
+    size_t i = 0;
+    for (const auto& kv : c->tuned) {
+        const TuneKey& k = kv.first;
+        const cwo_tuning& t = kv.second;
+        std::fprintf(f,
+                     " {\"kind\": %d, \"nx\": %d, \"ny\": %d, \"precision\": %d, \"flags\": %d, "
+                     "\"nz\": %d, \"row_form\": %d, \"zchunk\": %d, \"layout\": %d, "
+                     "\"us_per_plane\": %.3f}%s\n",
+                     k.kind, k.nx, k.ny, k.precision, k.flags, k.nz, t.row_form, t.zchunk, t.layout,
+                     (double)t.us_per_plane, ++i < c->tuned.size() ? "," : "");
+    }
+    std::fprintf(f, "]\n");
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
+    else std::remove(tmp.c_str());
 }
 
 cwo_status begin(cwo_ctx* c) {
@@ -470,7 +545,9 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
     }
     cwo::Storage sto;  // complex64: no intermediate scaling, 1/(Mx My) at the end
     sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);  // power of two: exact
-    sto.row_form = tuned_for(c, p, kind, 1).row_form;
+    const cwo_tuning tune = tuned_for(c, p, kind, 1);
+    sto.row_form = tune.row_form;
+    sto.layout = plane_layout(g, tune);
     if (p->precision != CWO_PREC_F32) {
         // FP16/BF16 storage: 2^-floor(log2(Mx)/2) before the row transform, 1/My in the
         // column pass, the rest of 1/Mx at the end (all powers of two); FP16 also scales
@@ -497,7 +574,7 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
         if (!masks) return st;
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_asm_shifted((float2*)buf, g.ny, g.my, g.mx, a, *shift,
-                                                       masks, twy, s);
+                                                       masks, twy, s, sto.layout);
                 }));
     } else if (kind == CWO_ANGULAR) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
@@ -624,18 +701,30 @@ cwo_status validate_jobs(const cwo_job* jobs, int njobs) {
     return CWO_OK;
 }
 
-// Consecutive jobs on the same field and geometry run as one z-stack; the rest singly.
-// Identical parameters (distance included) on another field: such jobs run as one batch
-// per pass (complex64 storage; FP16 storage scales each field by its own range).
-bool same_params(const cwo_job& a, const cwo_job& b) {
-    return a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx && a.p.dy == b.p.dy &&
-           a.p.wavelength == b.p.wavelength && a.p.z == b.p.z && a.p.kind == b.p.kind &&
-           a.p.precision == CWO_PREC_F32 && b.p.precision == CWO_PREC_F32 && a.p.flags == b.p.flags;
+// A job that can run as one plane of a mixed batch: complex64 storage, and for ASM a
+// transfer function in the fast form (the exact form runs singly).
+bool batchable(const cwo_job& j) {
+    if (j.p.precision != CWO_PREC_F32) return false;
+    if (j.p.kind == CWO_FRESNEL_CONV) return true;
+    if (j.p.kind != CWO_ANGULAR) return false;
+    const Geometry g = geometry(&j.p);
+    return cwo::asm_plane_tf(asm_scalars(&j.p, g, j.p.z), g.mx, g.my).form <= 1;
 }
 
-// Jobs [i, j) with identical parameters, one batch per pass, in chunks of at most kZChunk
-// planes that fit the budget. Every field is read by the first pass before the last pass
-// writes any output, so a batch must not read another batch member's output.
+// Consecutive jobs on the same field and geometry run as one z-stack; the rest singly.
+// Jobs of one geometry (sizes, pitch, flags) on different fields run as one batch per pass,
+// each plane with its own distance, wavelength and kind.
+bool same_params(const cwo_job& a, const cwo_job& b) {
+    return a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx && a.p.dy == b.p.dy &&
+           a.p.flags == b.p.flags && batchable(a) && batchable(b);
+}
+
+// Jobs [i, j) of one geometry, one batch per pass, in chunks of at most kZChunk planes
+// that fit the budget. Each plane gets the transfer function its single call would use:
+// the ASM fast form for its scalars, or Fresnel factors computed for the chunk's Fresnel
+// planes (the same kernel and arithmetic as the cached single-call factors). Every field
+// is read by the first pass before the last pass writes any output, so a batch must not
+// read another batch member's output.
 cwo_status batch_locked(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int n, hipStream_t s) {
     cwo_status st = CWO_OK;
     const cwo_params* p = &jobs[0].p;
@@ -644,49 +733,93 @@ cwo_status batch_locked(cwo_ctx* c, Workspace& ws, const cwo_job* jobs, int n, h
     if (!twx) return st;
     const float2* twy = twiddle_table(c, g.my, s, &st);
     if (!twy) return st;
-    const float2* h = nullptr;
-    if (p->kind == CWO_FRESNEL_CONV) {
-        h = fresnel_factors(c, ws, p, g, s, &st);
-        if (!h) return st;
-    }
     const size_t plane = (size_t)g.ny * g.mx;
+    const size_t len = (size_t)(g.mx + g.my);
+    int nfres = 0;
+    for (int k = 0; k < n; ++k) nfres += jobs[k].p.kind == CWO_FRESNEL_CONV;
     int chunk = std::min(n, cwo::kZChunk);
     if (ws.budget) {
-        const size_t other = ws.held() - ws.scratch.bytes;
-        const size_t fit = ws.budget > other ? (ws.budget - other) / (sizeof(float2) * plane) : 0;
+        const size_t other = ws.held() - ws.scratch.bytes - ws.ftab.bytes - ws.fwork.bytes;
+        const size_t fixed = nfres ? sizeof(double2) * len : 0;
+        const size_t per = sizeof(float2) * plane + (nfres ? sizeof(float2) * len : 0);
+        const size_t fit = ws.budget > other + fixed ? (ws.budget - other - fixed) / per : 0;
         if (fit == 0) return CWO_ERR_NOMEM;
         chunk = (int)std::min<size_t>((size_t)chunk, fit);
     }
     float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * plane * (size_t)chunk, &st);
     if (!buf) return st;
+    float2* ftab = nullptr;
+    double2* work = nullptr;
+    if (nfres) {
+        ftab = (float2*)ensure(c, ws, ws.ftab, sizeof(float2) * len * (size_t)std::min(chunk, nfres), &st);
+        if (!ftab) return st;
+        work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len, &st);
+        if (!work) return st;
+    }
     const float scale = 1.0f / ((float)g.mx * (float)g.my);
-    const cwo::AsmScalars a = asm_scalars(p, g, p->z);
+    const int layout = cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
+    const bool analytic = (p->flags & CWO_FLAG_FRESNEL_TF) != 0;
     for (int k0 = 0; k0 < n; k0 += chunk) {
         const int nb = std::min(chunk, n - k0);
         cwo::InTable ins;
         cwo::OutTable outs;
+        cwo::PlaneTF tab[cwo::kZChunk];
+        std::memset(tab, 0, sizeof(tab));
+        cwo::FresnelPlanes fp;
+        std::memset(&fp, 0, sizeof(fp));
+        fp.mx = g.mx;
+        fp.nx = g.nx;
+        fp.my = g.my;
+        fp.ny = g.ny;
+        fp.dx = p->dx;
+        fp.dy = p->dy;
+        fp.analytic = analytic;
         for (int k = 0; k < cwo::kZChunk; ++k) {
             ins.in[k] = k < nb ? (const float2*)jobs[k0 + k].in : nullptr;
             outs.out[k] = k < nb ? (float2*)jobs[k0 + k].out : nullptr;
         }
+        for (int k = 0; k < nb; ++k) {
+            const cwo_params* q = &jobs[k0 + k].p;
+            if (q->kind == CWO_ANGULAR) {
+                tab[k] = cwo::asm_plane_tf(asm_scalars(q, g, q->z), g.mx, g.my);
+            } else {
+                const int f = fp.nz++;
+                fp.inv2lz[f] = 0.5 / (q->wavelength * q->z);
+                fp.hlz[f] = 0.5 * q->wavelength * q->z;
+                if (analytic)
+                    phase_constant(q->wavelength, q->z, &fp.cre[f], &fp.cim[f]);
+                else
+                    fresnel_constant(q->dx, q->dy, q->wavelength, q->z, &fp.cre[f], &fp.cim[f]);
+                tab[k].form = 3;
+                tab[k].h = ftab + (size_t)f * len;
+            }
+        }
+        if (fp.nz > 0)
+            CWO_HIP(c, timed(c, CWO_STAGE_TABLES, s,
+                             [&] { return cwo::launch_fresnel_planes(work, ftab, fp, s); }));
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
-                    return cwo::launch_row_fwd_tab(ins, buf, g.nx, g.ny, g.mx, nb, plane, twx, s);
+                    return cwo::launch_row_fwd_tab(ins, buf, g.nx, g.ny, g.mx, nb, plane, twx, s,
+                                                   layout);
                 }));
-        CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return p->kind == CWO_ANGULAR
-                               ? cwo::launch_col_asm(buf, g.ny, g.my, g.mx, nb, plane, a, twy, s)
-                               : cwo::launch_col_fresnel(buf, g.ny, g.my, g.mx, nb, plane, h,
-                                                         h + g.mx, cwo::Storage{}, twy, s);
-                }));
+        // one column launch per transfer-function form present
+        bool present[4] = {false, false, false, false};
+        for (int k = 0; k < nb; ++k) present[tab[k].form] = true;
+        for (int form : {0, 1, 3}) {
+            if (!present[form]) continue;
+            CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
+                        return cwo::launch_col_mixed(buf, g.ny, g.my, g.mx, nb, plane, tab, form,
+                                                     twy, s, layout);
+                    }));
+        }
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
                     return cwo::launch_row_inv_tab(buf, outs, g.nx, g.ny, g.mx, nb, plane, scale,
-                                                   twx, s);
+                                                   twx, s, layout);
                 }));
     }
     return CWO_OK;
 }
 
-// Length of the run of jobs from i with identical parameters whose inputs are all
+// Length of the run of jobs from i of one geometry (same_params) whose inputs are all
 // different and none of which reads another member's output.
 int batch_run(const cwo_job* jobs, int i, int njobs) {
     int j = i + 1;
@@ -702,7 +835,7 @@ int batch_run(const cwo_job* jobs, int i, int njobs) {
 }
 
 // How run_jobs groups a job list: consecutive jobs on one field with one geometry form a
-// z-stack; runs of identical parameters on distinct fields a batch; the rest run singly.
+// z-stack; runs of one geometry on distinct fields a batch; the rest run singly.
 struct Group {
     enum Type { SINGLE, ZSTACK, BATCH } type;
     int i, j;  // jobs [i, j)
@@ -770,9 +903,17 @@ WsNeed jobs_need(cwo_ctx* c, const cwo_job* jobs, int njobs) {
                 w.ftab = std::max(w.ftab, sizeof(float2) * len * (size_t)zc);
                 w.fwork = std::max(w.fwork, sizeof(double2) * len);
             }
+        } else if (gr.type == Group::BATCH) {
+            const int nb = std::min(n, cwo::kZChunk);
+            int nf = 0;
+            for (int k = gr.i; k < gr.j; ++k) nf += jobs[k].p.kind == CWO_FRESNEL_CONV;
+            w.scratch = std::max(w.scratch, sizeof(float2) * plane * (size_t)nb);
+            if (nf) {
+                w.ftab = std::max(w.ftab, sizeof(float2) * len * (size_t)std::min(nf, nb));
+                w.fwork = std::max(w.fwork, sizeof(double2) * len);
+            }
         } else {
-            const size_t planes = gr.type == Group::BATCH ? (size_t)std::min(n, cwo::kZChunk) : 1;
-            w.scratch = std::max(w.scratch, elem_bytes(p->precision) * plane * planes);
+            w.scratch = std::max(w.scratch, elem_bytes(p->precision) * plane);
             if (p->precision == CWO_PREC_F16_STORAGE)
                 w.rwork = std::max(w.rwork, sizeof(float) * (2 + cwo::kRangeBlocks));
             if (fres) {
@@ -1180,6 +1321,7 @@ cwo_status cwo_create(cwo_ctx** ctx, int device, size_t hbm_budget_bytes) {
     c->device = device;
     c->budget = hbm_budget_bytes;
     c->ws.budget = hbm_budget_bytes;
+    load_tune_cache(c);
     *ctx = c;
     return CWO_OK;
 }
@@ -1235,6 +1377,7 @@ cwo_status cwo_asm_noalloc(cwo_ctx* c, const cwo_params* p, const void* in, void
     CWO_HIP(c, cwo::launch_twiddles(twy, g.my, s));
     cwo::Storage sto;
     sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
+    sto.layout = cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
     const cwo::AsmScalars a = asm_scalars(p, g, p->z);
     CWO_HIP(c, cwo::launch_row_fwd((const float2*)in, buf, g.nx, g.ny, g.mx, 1, 0, 0, sto, twx, s));
     CWO_HIP(c, cwo::launch_col_asm(buf, g.ny, g.my, g.mx, 1, 0, a, sto, twy, s));
@@ -1494,6 +1637,10 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
     const Geometry g = geometry(p);
     const bool half = !(p->flags & CWO_FLAG_NOPAD);
     std::vector<int> forms = (half && g.mx >= 1024) ? std::vector<int>{1, 2} : std::vector<int>{0};
+    // single planes: the row-major and the tiled plane where tiles are possible (the tiled
+    // row passes have one form)
+    std::vector<int> layouts{0};
+    if (nz == 1 && tiles_possible(g)) layouts = {1, 2};
     std::vector<int> chunks{0};
     if (nz > 1) {
         chunks.clear();
@@ -1510,11 +1657,15 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
                        : zstack_locked(c, c->ws, p, kind, zs.data(), nz, in, outs.data(), s);
     };
     hipEvent_t a = take_event(c), b = take_event(c);
-    cwo_tuning found{0, 0, 0.0f};
+    cwo_tuning found{0, 0, 0.0f, 0};
     float best_ms = -1.0f;
-    for (int f : forms) {
+    std::vector<std::pair<int, int>> cands;
+    for (int lay : layouts)
+        for (int f : (lay == 2 ? std::vector<int>{0} : forms)) cands.push_back({lay, f});
+    for (const auto& lf : cands) {
+        const int f = lf.second;
         for (int zc : chunks) {
-            const cwo_tuning cand{f, zc, 0.0f};
+            const cwo_tuning cand{f, zc, 0.0f, lf.first};
             set_tuned(c, key, &cand);
             st = run();  // warm-up: allocations and tables
             if (st != CWO_OK) break;
@@ -1531,7 +1682,7 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
             ms /= kReps;
             if (best_ms < 0.0f || ms < best_ms) {
                 best_ms = ms;
-                found = cwo_tuning{f, zc, (float)(1000.0 * ms / nz)};
+                found = cwo_tuning{f, zc, (float)(1000.0 * ms / nz), lf.first};
             }
         }
         if (st != CWO_OK) break;
@@ -1543,7 +1694,27 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
         return st;
     }
     set_tuned(c, key, &found);
+    save_tune_cache(c);
     if (best) *best = found;
+    return CWO_OK;
+}
+
+cwo_status cwo_set_tuning(cwo_ctx* c, const cwo_params* p, int32_t nz, const cwo_tuning* t) {
+    if (!c || !p || nz < 1) return CWO_ERR_INVALID;
+    const int kind = p->kind;
+    cwo_status st = validate_geometry(p, kind, nz == 1);
+    if (st != CWO_OK) return st;
+    const TuneKey key = tune_key(p, kind, nz);
+    if (!t) {
+        set_tuned(c, key, nullptr);
+        return CWO_OK;
+    }
+    if (t->row_form < 0 || t->row_form > 2 || t->zchunk < 0 || t->zchunk > cwo::kZChunk ||
+        t->layout < 0 || t->layout > 2 || !(t->us_per_plane >= 0.0f))
+        return CWO_ERR_INVALID;
+    if (t->layout == 2 && !(nz == 1 && tiles_possible(geometry(p)))) return CWO_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(c->mu);
+    set_tuned(c, key, t);
     return CWO_OK;
 }
 
@@ -1605,6 +1776,7 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     cwo::GsScale g2, g1;  // row passes after the +z and the -z column pass
     sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
     g2.scale = g1.scale = sto.out_scale;
+    sto.layout = g2.layout = g1.layout = cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
     if (p->precision != CWO_PREC_F32) {
         sto.prec = g2.prec = g1.prec = p->precision == CWO_PREC_F16_STORAGE ? 1 : 2;
         const int kx = ilog2(g.mx) / 2;

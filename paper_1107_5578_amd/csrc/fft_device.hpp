@@ -127,21 +127,36 @@ __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2&
     a3 = csub(t1, t3);
 }
 
+// DFT of 4 points of which the last two are zero: 8 additions instead of 16.
+template <int DIR>
+__device__ __forceinline__ void dft4_zin(float2& a0, float2& a1, float2& a2, float2& a3) {
+    const float2 x0 = a0, x1 = a1, r = rot90<DIR>(a1);
+    a0 = cadd(x0, x1);
+    a2 = csub(x0, x1);
+    a1 = cadd(x0, r);
+    a3 = csub(x0, r);
+}
+
 // DFT of R points held in v[OFF + STRIDE*k], k < R, result in the same slots in natural order.
-template <int R, int DIR, int OFF = 0, int STRIDE = 1, int N>
+// ZIN: the inputs k >= R/2 are known to be zero (the zero-padded half of a transform's
+// first pass) and are neither read nor added; each half-size DFT of the decimation in
+// time then has a zero upper half as well.
+template <int R, int DIR, int OFF = 0, int STRIDE = 1, bool ZIN = false, int N>
 __device__ __forceinline__ void dft(float2 (&v)[N]) {
     static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "radix");
     if constexpr (R == 1) {
         return;
     } else if constexpr (R == 2) {
-        dft2<DIR>(v[OFF], v[OFF + STRIDE]);
+        if constexpr (ZIN) v[OFF + STRIDE] = v[OFF];
+        else dft2<DIR>(v[OFF], v[OFF + STRIDE]);
     } else if constexpr (R == 4) {
-        dft4<DIR>(v[OFF], v[OFF + STRIDE], v[OFF + 2 * STRIDE], v[OFF + 3 * STRIDE]);
+        if constexpr (ZIN) dft4_zin<DIR>(v[OFF], v[OFF + STRIDE], v[OFF + 2 * STRIDE], v[OFF + 3 * STRIDE]);
+        else dft4<DIR>(v[OFF], v[OFF + STRIDE], v[OFF + 2 * STRIDE], v[OFF + 3 * STRIDE]);
     } else if constexpr (R == 8 || R == 32) {
         // radix-2 decimation in time over two half-size DFTs
         constexpr int H = R / 2;
-        dft<H, DIR, OFF, 2 * STRIDE>(v);           // even samples
-        dft<H, DIR, OFF + STRIDE, 2 * STRIDE>(v);  // odd samples
+        dft<H, DIR, OFF, 2 * STRIDE, ZIN>(v);           // even samples
+        dft<H, DIR, OFF + STRIDE, 2 * STRIDE, ZIN>(v);  // odd samples
         float2 t[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) t[k] = v[OFF + k * STRIDE];
@@ -155,10 +170,11 @@ __device__ __forceinline__ void dft(float2 (&v)[N]) {
         for (int k = 0; k < R; ++k) v[OFF + k * STRIDE] = o[k];
     } else {  // R == 16: 4 x 4
         // stage 1: for each n2, DFT4 over n1 of x[4*n1 + n2]; result Y[n2][k1] kept at slot 4*k1 + n2
-        dft4<DIR>(v[OFF + 0 * STRIDE], v[OFF + 4 * STRIDE], v[OFF + 8 * STRIDE], v[OFF + 12 * STRIDE]);
-        dft4<DIR>(v[OFF + 1 * STRIDE], v[OFF + 5 * STRIDE], v[OFF + 9 * STRIDE], v[OFF + 13 * STRIDE]);
-        dft4<DIR>(v[OFF + 2 * STRIDE], v[OFF + 6 * STRIDE], v[OFF + 10 * STRIDE], v[OFF + 14 * STRIDE]);
-        dft4<DIR>(v[OFF + 3 * STRIDE], v[OFF + 7 * STRIDE], v[OFF + 11 * STRIDE], v[OFF + 15 * STRIDE]);
+        // (with ZIN, x[4*n1 + n2] = 0 for n1 >= 2)
+        dft<4, DIR, OFF + 0 * STRIDE, 4 * STRIDE, ZIN>(v);
+        dft<4, DIR, OFF + 1 * STRIDE, 4 * STRIDE, ZIN>(v);
+        dft<4, DIR, OFF + 2 * STRIDE, 4 * STRIDE, ZIN>(v);
+        dft<4, DIR, OFF + 3 * STRIDE, 4 * STRIDE, ZIN>(v);
         // twiddles W16^(n2*k1) on slot 4*k1 + n2
         float2 y[16];
         [&]<int... S>(std::integer_sequence<int, S...>) {
@@ -272,10 +288,14 @@ __device__ __forceinline__ void lds_get(const float2* lds, int slot, float2 (&x)
 // (intermediate pass) or back into registers in natural order (last pass). With SPLIT
 // (P == 2 only) the LDS holds one transform at a time: transform 0 is written here and
 // transform 1's outputs are kept in `held` for the second half of the exchange.
-template <int M, int E, int P, int RP, int NS, bool LAST, int DIR, bool SPLIT, bool PRE>
+// ZIN (first pass only, NS == 1): the butterfly inputs kk >= RP/2 are the elements
+// b + kk*M/RP >= M/2, the zero-padded half of the sequence; they are not read.
+template <int M, int E, int P, int RP, int NS, bool LAST, int DIR, bool SPLIT, bool PRE,
+          bool ZIN = false>
 __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, int j,
                                               const float2* __restrict__ tw,
                                               const float2 (&wpre)[E], float2 (&held)[E]) {
+    static_assert(!ZIN || NS == 1, "zero inputs are known in the first pass only");
     constexpr int T = M / E;
     constexpr int NB = E / RP;  // butterflies per thread and transform
     float2 out[P][E];
@@ -293,12 +313,12 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
 #pragma unroll
         for (int p = 0; p < P; ++p) {
 #pragma unroll
-            for (int kk = 0; kk < RP; ++kk) u[p][kk] = v[p][i + kk * NB];
+            for (int kk = 0; kk < (ZIN ? RP / 2 : RP); ++kk) u[p][kk] = v[p][i + kk * NB];
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int kk = 1; kk < RP; ++kk) u[p][kk] = ctw<DIR>(u[p][kk], w[kk]);
             }
-            dft<RP, DIR>(u[p]);
+            dft<RP, DIR, 0, 1, ZIN>(u[p]);
         }
         if constexpr (LAST) {
 #pragma unroll
@@ -335,7 +355,8 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
 // v[p][r] = X_p[j + r*T]. All threads of the block must call it (block barriers).
 // SPLIT halves the LDS footprint (one float2 slot per element) at the cost of two more
 // barriers per exchange.
-template <int M, int E, int P, int DIR, bool SPLIT = false, bool PRE = false>
+// ZIN: the elements M/2 .. M-1 of the input are zero (whatever the registers hold).
+template <int M, int E, int P, int DIR, bool SPLIT = false, bool PRE = false, bool ZIN = false>
 __device__ __forceinline__ void fft_impl(float2 (&v)[P][E], float2* lds, int j,
                                          const float2* __restrict__ tw,
                                          const TwCache<M, E>* twc) {
@@ -348,11 +369,12 @@ __device__ __forceinline__ void fft_impl(float2 (&v)[P][E], float2* lds, int j,
              constexpr int RP = PL::radix(p);
              constexpr int NS = PL::ns(p);
              constexpr bool LAST = (p == PL::PASSES - 1);
+             constexpr bool Z = ZIN && p == 0;
              float2 held[E];
              if constexpr (PRE)
-                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, true>(v, lds, j, tw, twc->w[p], held);
+                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, true, Z>(v, lds, j, tw, twc->w[p], held);
              else
-                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, false>(v, lds, j, tw, held, held);
+                 stockham_pass<M, E, P, RP, NS, LAST, DIR, SPLIT, false, Z>(v, lds, j, tw, held, held);
              if constexpr (!LAST) {
                  if constexpr (SPLIT) {
                      lds_barrier();
@@ -401,6 +423,14 @@ template <int M, int E, int P, int DIR, bool SPLIT = false>
 __device__ __forceinline__ void fft(float2 (&v)[P][E], float2* lds, int j,
                                     const TwCache<M, E>& twc) {
     fft_impl<M, E, P, DIR, SPLIT, true>(v, lds, j, nullptr, &twc);
+}
+
+// Forward transform of a zero-padded sequence (elements M/2 .. M-1 zero): the first
+// pass skips the additions of the zero half; the registers of those elements are not read.
+template <int M, int E, int P, int DIR, bool SPLIT = false>
+__device__ __forceinline__ void fft_zpad(float2 (&v)[P][E], float2* lds, int j,
+                                         const TwCache<M, E>& twc) {
+    fft_impl<M, E, P, DIR, SPLIT, true, true>(v, lds, j, nullptr, &twc);
 }
 
 }  // namespace cwo

@@ -31,11 +31,13 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
     const float* arow = amp + (size_t)(valid ? row : 0) * nx;
     float2* my_lds = lds + sub * lds_elems<M>();
     if (dyn_inv) scale *= *dyn_inv;
+    TwCache<M, E> twc;
+    twc.load(j, tw);
     float2 v[1][E];
 #pragma unroll
     for (int r = 0; r < E; ++r)
         v[0][r] = valid ? ST::dec(srow[j + r * T]) : make_float2(0.f, 0.f);
-    fft<M, E, 1, INV>(v, my_lds, j, tw);
+    fft<M, E, 1, INV>(v, my_lds, j, twc);
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -90,10 +92,139 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
 #pragma unroll
         for (int r = 0; r < E; ++r) v[0][r] = make_float2(v[0][r].x * fwd_scale, v[0][r].y * fwd_scale);
     }
-    fft<M, E, 1, FWD>(v, my_lds, j, tw);
+    if constexpr (HALF) fft_zpad<M, E, 1, FWD>(v, my_lds, j, twc);
+    else fft<M, E, 1, FWD>(v, my_lds, j, twc);
     if (valid) {
 #pragma unroll
         for (int r = 0; r < E; ++r) srow[j + r * T] = ST::enc(v[0][r]);
+    }
+}
+
+// The same on the tiled spectrum plane (padded rows, Mx = 2Nx): groups of RPB rows per
+// block, a resident grid (the blocks of one XCD take that XCD's contiguous range of
+// groups), the next group's tile rows loaded into registers while the current group is
+// processed. Per group: tile rows regrouped into rows in LDS, inverse transform, crop,
+// constraint and the row's error partial; then either the constrained field to out, or
+// the re-padded forward transform regrouped by tile and stored back in place (each block
+// reads and writes only its own groups' tile rows).
+template <int M, class ST>
+__global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
+    typename ST::E* __restrict__ spec, const float* __restrict__ amp, float2* __restrict__ out,
+    double* __restrict__ num, int nx, int ny, float scale, const float* __restrict__ dyn_inv,
+    float fwd_scale, const float* __restrict__ dyn_fwd, const float2* __restrict__ tw) {
+    using C = TileRowCfg<M>;
+    using SE = typename ST::E;
+    using K = TileChunks<M, SE>;
+    using PK = Pack<SE, K::CE>;
+    constexpr int E = C::E, T = C::T, NL = E / 2;
+    __shared__ float2 lds[C::LDS];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    float2* my_lds = lds + sub * lds_elems<M>();
+    if (dyn_inv) scale *= *dyn_inv;
+    if (dyn_fwd) fwd_scale *= *dyn_fwd;
+    const int groups = ny / C::RPB;
+    const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, groups);
+    TwCache<M, E> twc;
+    twc.load(j, tw);
+    auto load = [&](int g, PK (&d)[K::CPT]) {
+        const int y0 = g * C::RPB;
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) {
+            const int c = tid + k * C::THREADS;
+            const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
+            d[k] = *reinterpret_cast<const PK*>(spec + ((size_t)t * ny + y0) * kTileW + q * K::CE);
+        }
+    };
+    PK cur[K::CPT], nxt[K::CPT];
+    int g = ir.first;
+    if (g < ir.end) load(g, cur);
+    for (; g < ir.end; g += ir.step) {
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) {
+            const int c = tid + k * C::THREADS;
+#pragma unroll
+            for (int e = 0; e < K::CE; ++e) lds[c * K::CE + e] = ST::dec(cur[k].e[e]);
+        }
+        lds_barrier();
+        float2 v[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = j + r * T;
+            v[0][r] = lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)];
+        }
+        lds_barrier();
+        if (g + ir.step < ir.end) load(g + ir.step, nxt);
+        const int y0 = g * C::RPB, row = y0 + sub;
+        const float* arow = amp + (size_t)row * nx;
+        fft<M, E, 1, INV>(v, my_lds, j, twc);
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r < NL) {
+                const float a = arow[j + r * T];
+                const float re = v[0][r].x * scale, im = v[0][r].y * scale;
+                const float m2 = re * re + im * im;
+                float2 c;
+                if (m2 > 0.f) {
+                    const float mag = __fsqrt_rn(m2);
+                    const float f = a / mag;
+                    c = make_float2(re * f, im * f);
+                    const double d = (double)mag - (double)a;
+                    acc += d * d;
+                } else {
+                    c = make_float2(a, 0.f);
+                    acc += (double)a * (double)a;
+                }
+                v[0][r] = c;
+            } else {
+                v[0][r] = make_float2(0.f, 0.f);
+            }
+        }
+        if (num) {
+            // deterministic per-row sum: lane partials through LDS, summed in index order
+            double* red = reinterpret_cast<double*>(my_lds);
+            lds_barrier();
+            red[j] = acc;
+            lds_barrier();
+            if (j == 0) {
+                double t = 0.0;
+                for (int i = 0; i < T; ++i) t += red[i];
+                num[row] = t;
+            }
+            lds_barrier();
+        }
+        if (out) {
+            float2* orow = out + (size_t)row * nx;
+#pragma unroll
+            for (int r = 0; r < NL; ++r) orow[j + r * T] = v[0][r];
+        } else {
+            if (fwd_scale != 1.0f) {
+#pragma unroll
+                for (int r = 0; r < E; ++r)
+                    v[0][r] = make_float2(v[0][r].x * fwd_scale, v[0][r].y * fwd_scale);
+            }
+            fft_zpad<M, E, 1, FWD>(v, my_lds, j, twc);
+            lds_barrier();
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int x = j + r * T;
+                lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)] = v[0][r];
+            }
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < K::CPT; ++k) {
+                const int c = tid + k * C::THREADS;
+                const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
+                PK pk;
+#pragma unroll
+                for (int e = 0; e < K::CE; ++e) pk.e[e] = ST::enc(lds[c * K::CE + e]);
+                *reinterpret_cast<PK*>(spec + ((size_t)t * ny + y0) * kTileW + q * K::CE) = pk;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) cur[k] = nxt[k];
     }
 }
 
@@ -138,9 +269,24 @@ namespace {
 template <class ST>
 hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int nx, int ny,
                     int mx, float scale, const float* dyn_inv, float fwd_scale,
-                    const float* dyn_fwd, const float2* tw, hipStream_t s) {
+                    const float* dyn_fwd, const float2* tw, hipStream_t s, int layout) {
     using SE = typename ST::E;
     const bool half = (mx == 2 * nx);
+    if (layout == 1) {
+        if (!half) return hipErrorInvalidValue;
+        CWO_DISPATCH_M(mx, {
+            if constexpr (MM >= 2048) {
+                using C = TileRowCfg<MM>;
+                auto k = k_row_gs_tile<MM, ST>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),
+                                   dim3(C::THREADS), 0, s, (SE*)spec, amp, out, num, nx, ny,
+                                   scale, dyn_inv, fwd_scale, dyn_fwd, tw);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        });
+        return hipGetLastError();
+    }
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB);
@@ -160,13 +306,13 @@ hipError_t launch_row_gs(void* spec, const float* amp, float2* out, double* num,
     switch (gsc.prec) {
         case 0:
             return row_gs_t<StF32>(spec, amp, out, num, nx, ny, mx, gsc.scale, gsc.dyn_inv,
-                                   gsc.fwd_scale, gsc.dyn_fwd, tw, s);
+                                   gsc.fwd_scale, gsc.dyn_fwd, tw, s, gsc.layout);
         case 1:
             return row_gs_t<StF16>(spec, amp, out, num, nx, ny, mx, gsc.scale, gsc.dyn_inv,
-                                   gsc.fwd_scale, gsc.dyn_fwd, tw, s);
+                                   gsc.fwd_scale, gsc.dyn_fwd, tw, s, gsc.layout);
         case 2:
             return row_gs_t<StBF16>(spec, amp, out, num, nx, ny, mx, gsc.scale, gsc.dyn_inv,
-                                    gsc.fwd_scale, gsc.dyn_fwd, tw, s);
+                                    gsc.fwd_scale, gsc.dyn_fwd, tw, s, gsc.layout);
     }
     return hipErrorInvalidValue;
 }

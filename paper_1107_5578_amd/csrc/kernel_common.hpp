@@ -25,6 +25,54 @@ struct RowCfg {
     static constexpr int THREADS = T * RPB;
 };
 
+// ---- storage layout of the padded spectrum plane between the passes -------------
+//
+// Row-major: element (y, x) of the [Ny][Mx] plane at y*Mx + x. Tiled: the columns are
+// grouped in tiles of kTileW and each tile stores its rows one after another, element
+// (y, x) at ((x / kTileW)*Ny + y)*kTileW + x % kTileW. In the tiled plane the successive
+// rows of a column pair lie 8*kTileW bytes apart, so a wavefront of the column pass reads
+// and writes a few whole cache lines instead of one line per lane; the row passes move
+// whole tile rows of several rows at a time through LDS (RPB rows per block).
+constexpr int kTileW = 4;
+
+struct LayRow {
+    int mx;
+    __device__ __forceinline__ size_t at(int y, int x) const { return (size_t)y * mx + x; }
+};
+struct LayTile {
+    int ny;
+    __device__ __forceinline__ size_t at(int y, int x) const {
+        return ((size_t)(x / kTileW) * ny + y) * kTileW + (x % kTileW);
+    }
+};
+
+// Row passes on the tiled plane: RPB rows per block, so that a block moves RPB*kTileW
+// contiguous elements per tile (64 bytes of complex64 with two rows); the transform
+// results go through LDS once more to be regrouped by tile.
+template <int M>
+struct TileRowCfg {
+    static constexpr int E = 16;
+    static constexpr int T = M / E;
+    static constexpr int RPB = (T >= 512) ? 1 : (T >= 128 ? 2 : 256 / T);
+    static constexpr int THREADS = T * RPB;
+    static constexpr int TS = kTileW * RPB;         // LDS float2 per tile
+    static constexpr int XCH = RPB * lds_elems<M>();  // exchange buffers of the transforms
+    static constexpr int TRN = (M / kTileW) * TS;     // regrouping buffer
+    static constexpr int LDS = XCH > TRN ? XCH : TRN;
+};
+
+// A row group's tile rows move in 16-byte chunks of CE elements: chunk c of the group sits
+// at c*CE in the regrouping buffer (tile t = c / PER_TILE, tile-major) and at
+// (t*Ny + y0)*kTileW + (c % PER_TILE)*CE in the plane; CPT chunks per thread.
+template <int M, class SE>
+struct TileChunks {
+    using C = TileRowCfg<M>;
+    static constexpr int CE = 16 / (int)sizeof(SE);
+    static constexpr int PER_TILE = C::RPB * kTileW / CE;
+    static constexpr int CPT = (M / kTileW) * PER_TILE / C::THREADS;
+    static_assert(CPT * C::THREADS == (M / kTileW) * PER_TILE, "chunks");
+};
+
 // Column pass: each thread transforms two adjacent columns (16-byte loads and
 // stores, one 16-byte LDS slot per element pair); PAIRS column pairs per block.
 template <int M>

@@ -48,7 +48,15 @@ struct Storage {
     float out_scale = 1.0f;
     const float* dyn_inv = nullptr;
     int row_form = 0;  // row passes: 0 default, 1 persistent with prefetch, 2 one group per block
+    int layout = 0;    // padded plane between the passes: 0 row-major, 1 tiled (see tiled_ok)
 };
+
+// The tiled plane layout is taken for padded planes (Mx = 2Nx, My = 2Ny) with
+// 2048 <= Mx <= 4096 (at Mx = 8192 a block holds one row and its quarter-line tile rows
+// cost more in the row passes than the column pass gains: measured).
+inline bool tiled_ok(int nx, int ny, int mx, int my) {
+    return mx == 2 * nx && my == 2 * ny && mx >= 2048 && mx <= 4096;
+}
 
 constexpr int kRangeBlocks = 1024;
 // work[0] = 2^-e, work[1] = 2^e with e = the binary exponent of max(|re|, |im|) over the
@@ -69,10 +77,26 @@ hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t p
 // mx + my floats of scratch for the band masks.
 hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const AsmScalars& a,
                                   const AsmShift& sh, float* masks, const float2* tw,
-                                  hipStream_t s);
+                                  hipStream_t s, int layout = 0);
 hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
                               const float2* hx, const float2* hy, const Storage& st,
                               const float2* tw, hipStream_t s);
+// Column pass of a mixed batch: planes of one geometry in `buf` (plane stride `plane`),
+// plane k with the transfer function tf[k]. One call launches the column kernel of one
+// form over the planes of that form (none: no launch); complex64, n <= kZChunk.
+struct PlaneTF {
+    int form;               // 0, 1: ASM fast form, series to s^4 / s^9; 2: ASM exact (not
+                            // batched); 3: Fresnel
+    float c0;               // fast forms: zl reduced to [-0.5, 0.5]
+    double d0, d1, d2, d3;  // fast: lam_dfx, lam_dfy, zl, half_zl; exact: dfx, dfy, lam, zl
+    const float2* h;        // Fresnel: Hx (mx entries, with C), then Hy (my entries)
+};
+hipError_t launch_col_mixed(float2* buf, int ny, int my, int mx, int n, size_t plane,
+                            const PlaneTF* tf, int form, const float2* tw, hipStream_t s,
+                            int layout);
+// The angular-spectrum transfer function a single call takes for these scalars (the fast
+// form with its series length, or the exact form).
+PlaneTF asm_plane_tf(const AsmScalars& a, int mx, int my);
 hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, int batch,
                           size_t in_plane, size_t out_plane, const Storage& st, const float2* tw,
                           hipStream_t s);
@@ -87,7 +111,7 @@ hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx,
 
 // buf: batch planes of [ny][mx], column transform of length my (my = ny or 2*ny)
 hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                          const AsmScalars& a, const float2* tw, hipStream_t s);
+                          const AsmScalars& a, const float2* tw, hipStream_t s, int layout = 0);
 
 
 // in: [ny][mx] per plane; out: [ny][nx] per plane, scaled by `scale`
@@ -119,6 +143,7 @@ struct GsScale {
     const float* dyn_inv = nullptr;
     float fwd_scale = 1.0f;
     const float* dyn_fwd = nullptr;
+    int layout = 0;  // layout of spec: 0 row-major, 1 tiled
 };
 // Ping-pong iteration row kernel. For each of the ny rows of spec ([ny][mx] in the
 // storage of gsc.prec, the output of a column pass): inverse row FFT, keep the first nx
@@ -204,10 +229,10 @@ struct OutIntensity {
     }
 };
 hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
-                              size_t out_plane, const float2* tw, hipStream_t s);
+                              size_t out_plane, const float2* tw, hipStream_t s, int layout = 0);
 hipError_t launch_row_inv_tab(const float2* in, const OutTable& outs, int nx, int ny, int mx,
                               int batch, size_t in_plane, float scale, const float2* tw,
-                              hipStream_t s);
+                              hipStream_t s, int layout = 0);
 
 // Fresnel diffraction in Fourier form (Sec. 2.1.2): parameters of the chirp tables.
 struct FourierPlan {

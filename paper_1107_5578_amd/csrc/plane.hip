@@ -68,7 +68,8 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(IN ins,
 #pragma unroll
         for (int r = 0; r < E; ++r) v[0][r] = make_float2(v[0][r].x * f, v[0][r].y * f);
     }
-    fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+    if constexpr (HALF) fft_zpad<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+    else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
     if (valid) {
         typename ST::E* dst = out + blockIdx.y * out_plane + (size_t)row * M;
 #pragma unroll
@@ -115,7 +116,8 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd_pf(IN ins,
 #pragma unroll
         for (int r = 0; r < E; ++r)
             v[0][r] = r < NL ? make_float2(cur[r].x * f, cur[r].y * f) : make_float2(0.f, 0.f);
-        fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+        if constexpr (HALF) fft_zpad<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+        else fft<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
         const int w = g * C::RPB + sub;
         if (w < rows) {
             const int pl = w / ny, row = w - pl * ny;
@@ -213,6 +215,137 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_inv_pf(
     }
 }
 
+// ---- row passes on the tiled plane ----------------------------------------------
+
+// Row forward into the tiled plane (padded rows, Mx = 2Nx). A resident grid walks groups
+// of RPB consecutive rows of the batch (the blocks of one XCD take that XCD's contiguous
+// range of groups, so the rows that share a tile line are written through one L2); the
+// next group's field values are loaded into registers while the current group is
+// transformed. The RPB row spectra are then regrouped in LDS by tile, and each thread
+// stores whole tile rows: RPB*kTileW contiguous elements per tile and group.
+template <int M, class ST, class IN>
+__global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_fwd_tile(
+    IN ins, typename ST::E* __restrict__ out, int nx, int ny, int batch, size_t out_plane,
+    RowScale sc, const float2* __restrict__ tw) {
+    using C = TileRowCfg<M>;
+    constexpr int E = C::E, T = C::T, NL = E / 2;
+    using SE = typename ST::E;
+    using K = TileChunks<M, SE>;
+    using PK = Pack<SE, K::CE>;
+    __shared__ float2 lds[C::LDS];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    const float f = sc.dyn ? sc.in * *sc.dyn : sc.in;
+    const int groups = ny * batch / C::RPB;
+    const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, groups);
+    TwCache<M, E> twc;
+    twc.load(j, tw);
+    auto load = [&](int g, float2 (&d)[NL]) {
+        const int w = g * C::RPB + sub;  // row of the batch
+        const int pl = w / ny, row = w - pl * ny;
+        const float2* src = ins(pl) + (size_t)row * nx;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) d[r] = src[j + r * T];
+    };
+    float2 cur[NL], nxt[NL];
+    int g = ir.first;
+    if (g < ir.end) load(g, cur);
+    for (; g < ir.end; g += ir.step) {
+        if (g + ir.step < ir.end) load(g + ir.step, nxt);
+        float2 v[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+            v[0][r] = r < NL ? make_float2(cur[r].x * f, cur[r].y * f) : make_float2(0.f, 0.f);
+        fft_zpad<M, E, 1, FWD>(v, lds + sub * lds_elems<M>(), j, twc);
+        // regroup by tile (the barriers also keep the compiler from moving LDS accesses
+        // across the phases)
+        lds_barrier();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = j + r * T;
+            lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)] = v[0][r];
+        }
+        lds_barrier();
+        const int w0 = g * C::RPB, pl = w0 / ny, y0 = w0 - pl * ny;
+        SE* dst = out + pl * out_plane;
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) {
+            const int c = tid + k * C::THREADS;
+            const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
+            PK pk;
+#pragma unroll
+            for (int e = 0; e < K::CE; ++e) pk.e[e] = ST::enc(lds[c * K::CE + e]);
+            *reinterpret_cast<PK*>(dst + ((size_t)t * ny + y0) * kTileW + q * K::CE) = pk;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int r = 0; r < NL; ++r) cur[r] = nxt[r];
+    }
+}
+
+// Row inverse from the tiled plane: the mirror of k_row_fwd_tile. Each thread loads
+// whole tile rows of the next group while the current one is transformed; a group's
+// tile rows are regrouped in LDS into rows, transformed, cropped to the first Nx values
+// and scaled.
+template <int M, class OUT, class ST>
+__global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_inv_tile(
+    const typename ST::E* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
+    float scale, const float* __restrict__ dyn_inv, const float2* __restrict__ tw) {
+    using C = TileRowCfg<M>;
+    constexpr int E = C::E, T = C::T;
+    using SE = typename ST::E;
+    using K = TileChunks<M, SE>;
+    using PK = Pack<SE, K::CE>;
+    __shared__ float2 lds[C::LDS];
+    const int tid = threadIdx.x;
+    const int sub = tid / T, j = tid % T;
+    if (dyn_inv) scale *= *dyn_inv;
+    const int groups = ny * batch / C::RPB;
+    const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, groups);
+    TwCache<M, E> twc;
+    twc.load(j, tw);
+    auto load = [&](int g, PK (&d)[K::CPT]) {
+        const int w0 = g * C::RPB, pl = w0 / ny, y0 = w0 - pl * ny;
+        const SE* src = in + pl * in_plane;
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) {
+            const int c = tid + k * C::THREADS;
+            const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
+            d[k] = *reinterpret_cast<const PK*>(src + ((size_t)t * ny + y0) * kTileW + q * K::CE);
+        }
+    };
+    PK cur[K::CPT], nxt[K::CPT];
+    int g = ir.first;
+    if (g < ir.end) load(g, cur);
+    for (; g < ir.end; g += ir.step) {
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) {
+            const int c = tid + k * C::THREADS;
+#pragma unroll
+            for (int e = 0; e < K::CE; ++e) lds[c * K::CE + e] = ST::dec(cur[k].e[e]);
+        }
+        lds_barrier();
+        float2 v[1][E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int x = j + r * T;
+            v[0][r] = lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)];
+        }
+        lds_barrier();
+        if (g + ir.step < ir.end) load(g + ir.step, nxt);
+        fft<M, E, 1, INV>(v, lds + sub * lds_elems<M>(), j, twc);
+        const int w = g * C::RPB + sub;
+        const int pl = w / ny, row = w - pl * ny;
+        const size_t base = (size_t)row * nx;
+#pragma unroll
+        for (int r = 0; r < E / 2; ++r)
+            outs.put(pl, base + j + r * T, make_float2(v[0][r].x * scale, v[0][r].y * scale));
+#pragma unroll
+        for (int k = 0; k < K::CPT; ++k) cur[k] = nxt[k];
+    }
+}
+
 // ---- tables -------------------------------------------------------------------
 
 // tw[k] = exp(-2*pi*i*k/M), evaluated in FP64 and rounded once to FP32
@@ -234,9 +367,24 @@ hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
 template <class ST, class IN>
 static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int mx, int batch,
                                    size_t out_plane, RowScale sc, const float2* tw,
-                                   hipStream_t s, int form = 0) {
+                                   hipStream_t s, int form = 0, int layout = 0) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
+    if (layout == 1) {
+        if (!half) return hipErrorInvalidValue;
+        CWO_DISPATCH_M(mx, {
+            if constexpr (MM >= 2048) {
+                using C = TileRowCfg<MM>;
+                const int groups = ny * batch / C::RPB;
+                auto k = k_row_fwd_tile<MM, ST, IN>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        });
+        return hipGetLastError();
+    }
     // persistent form with prefetch where rows are long enough to fill whole blocks
     // (form 2 asks for one row group per block)
     if (half && mx >= 1024 && form != 2) {
@@ -271,9 +419,9 @@ hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, i
                           hipStream_t s) {
     const RowScale sc{st.in_scale, st.dyn_scale};
     switch (st.prec) {
-        case 0: return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
-        case 1: return launch_row_fwd_t<StF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
-        case 2: return launch_row_fwd_t<StBF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form);
+        case 0: return launch_row_fwd_t<StF32>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form, st.layout);
+        case 1: return launch_row_fwd_t<StF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form, st.layout);
+        case 2: return launch_row_fwd_t<StBF16>(InStrided{in, in_plane}, out, nx, ny, mx, batch, out_plane, sc, tw, s, st.row_form, st.layout);
     }
     return hipErrorInvalidValue;
 }
@@ -286,93 +434,34 @@ hipError_t launch_row_fwd(const float2* in, float2* out, int nx, int ny, int mx,
 }
 
 hipError_t launch_row_fwd_tab(const InTable& ins, float2* out, int nx, int ny, int mx, int batch,
-                              size_t out_plane, const float2* tw, hipStream_t s) {
+                              size_t out_plane, const float2* tw, hipStream_t s, int layout) {
     return launch_row_fwd_t<StF32>(ins, out, nx, ny, mx, batch, out_plane,
-                                   RowScale{1.0f, nullptr}, tw, s);
-}
-
-template <class HF, class ST>
-static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, size_t plane,
-                               const HF& hf, float hscale, const float2* tw, hipStream_t s) {
-    const bool half = (my == 2 * ny);
-    using SE = typename ST::E;
-    CWO_DISPATCH_M(my, {
-        using C = ColCfg<MM>;
-        const int items = (mx + C::COLS - 1) / C::COLS * batch;
-        if (half) {
-            hipLaunchKernelGGL((k_col<MM, true, HF, ST>), dim3(items), dim3(C::THREADS), 0, s,
-                               (SE*)buf, ny, mx, batch, plane, hf, hscale, tw);
-        } else if constexpr (std::is_same_v<ST, StF32>) {
-            hipLaunchKernelGGL((k_col<MM, false, HF, ST>), dim3(items), dim3(C::THREADS), 0, s,
-                               (SE*)buf, ny, mx, batch, plane, hf, hscale, tw);
-        } else {
-            return hipErrorInvalidValue;
-        }
-    });
-    return hipGetLastError();
-}
-
-template <class HF>
-static hipError_t launch_col_impl(void* buf, int ny, int my, int mx, int batch, size_t plane,
-                                  const HF& hf, const Storage& st, const float2* tw,
-                                  hipStream_t s) {
-    switch (st.prec) {
-        case 0: return launch_col_t<HF, StF32>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
-        case 1: return launch_col_t<HF, StF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
-        case 2: return launch_col_t<HF, StBF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t plane,
-                          const AsmScalars& a, const Storage& st, const float2* tw, hipStream_t s) {
-    // largest s = (lambda fx)^2 + (lambda fy)^2 on the grid: the Nyquist corner
-    const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
-    const double smax = sx * sx + sy * sy;
-    if (smax <= kAsmFastMaxS) {
-        auto fill = [&](auto& hf) {
-            hf.lam_dfx = a.lam * a.dfx;
-            hf.lam_dfy = a.lam * a.dfy;
-            hf.zl = a.zl;
-            hf.half_zl = 0.5 * a.zl;
-            hf.c0 = (float)(a.zl - std::nearbyint(a.zl));
-            hf.mx = mx;
-            hf.my = my;
-        };
-        // the series to s^4 suffices when |zl| times its remainder, at most
-        // c_5 smax^5/(1 - smax) with c_5 = 7/256, stays below 2^-28 revolution
-        const double s5 = smax * smax * smax * smax * smax;
-        if (std::fabs(a.zl) * (7.0 / 256.0) * s5 / (1.0 - smax) <= std::ldexp(1.0, -28)) {
-            AsmHFastN<4> hf;
-            fill(hf);
-            return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
-        }
-        AsmHFastN<9> hf;
-        fill(hf);
-        return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
-    }
-    AsmH hf{a.dfx, a.dfy, a.lam, a.zl, mx, my};
-    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
-}
-
-hipError_t launch_col_asm(float2* buf, int ny, int my, int mx, int batch, size_t plane,
-                          const AsmScalars& a, const float2* tw, hipStream_t s) {
-    return launch_col_asm((void*)buf, ny, my, mx, batch, plane, a, Storage{}, tw, s);
-}
-
-hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
-                              const float2* hx, const float2* hy, const Storage& st,
-                              const float2* tw, hipStream_t s) {
-    FresnelH hf{hx, hy};
-    return launch_col_impl(buf, ny, my, mx, batch, plane, hf, st, tw, s);
+                                   RowScale{1.0f, nullptr}, tw, s, 0, layout);
 }
 
 template <class OUT, class ST>
 static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int ny, int mx,
                                    int batch, size_t in_plane, float scale, const float* dyn_inv,
-                                   const float2* tw, hipStream_t s, int form = 0) {
+                                   const float2* tw, hipStream_t s, int form = 0,
+                                   int layout = 0) {
     const bool half = (mx == 2 * nx);
     using SE = typename ST::E;
+    if (layout == 1) {
+        if (!half) return hipErrorInvalidValue;
+        CWO_DISPATCH_M(mx, {
+            if constexpr (MM >= 2048) {
+                using C = TileRowCfg<MM>;
+                const int groups = ny * batch / C::RPB;
+                auto k = k_row_inv_tile<MM, OUT, ST>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
+                                   dyn_inv, tw);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        });
+        return hipGetLastError();
+    }
     if (half && mx >= 1024 && form != 2) {
         CWO_DISPATCH_M(mx, {
             if constexpr (MM >= 1024) {
@@ -404,9 +493,9 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
 template <class OUT>
 static hipError_t launch_row_inv_impl(const float2* in, const OUT& outs, int nx, int ny, int mx,
                                       int batch, size_t in_plane, float scale, const float2* tw,
-                                      hipStream_t s) {
+                                      hipStream_t s, int layout = 0) {
     return launch_row_inv_t<OUT, StF32>(in, outs, nx, ny, mx, batch, in_plane, scale, nullptr, tw,
-                                        s);
+                                        s, 0, layout);
 }
 
 hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx, int batch,
@@ -418,8 +507,8 @@ hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx,
 
 hipError_t launch_row_inv_tab(const float2* in, const OutTable& outs, int nx, int ny, int mx,
                               int batch, size_t in_plane, float scale, const float2* tw,
-                              hipStream_t s) {
-    return launch_row_inv_impl(in, outs, nx, ny, mx, batch, in_plane, scale, tw, s);
+                              hipStream_t s, int layout) {
+    return launch_row_inv_impl(in, outs, nx, ny, mx, batch, in_plane, scale, tw, s, layout);
 }
 
 hipError_t launch_row_inv_intensity(const void* in, float* out, int nx, int ny, int mx,
@@ -428,13 +517,13 @@ hipError_t launch_row_inv_intensity(const void* in, float* out, int nx, int ny, 
     switch (st.prec) {
         case 0:
             return launch_row_inv_t<OutIntensity, StF32>(in, o, nx, ny, mx, 1, 0, st.out_scale,
-                                                         st.dyn_inv, tw, s, st.row_form);
+                                                         st.dyn_inv, tw, s, st.row_form, st.layout);
         case 1:
             return launch_row_inv_t<OutIntensity, StF16>(in, o, nx, ny, mx, 1, 0, st.out_scale,
-                                                         st.dyn_inv, tw, s, st.row_form);
+                                                         st.dyn_inv, tw, s, st.row_form, st.layout);
         case 2:
             return launch_row_inv_t<OutIntensity, StBF16>(in, o, nx, ny, mx, 1, 0, st.out_scale,
-                                                          st.dyn_inv, tw, s, st.row_form);
+                                                          st.dyn_inv, tw, s, st.row_form, st.layout);
     }
     return hipErrorInvalidValue;
 }
@@ -447,15 +536,15 @@ hipError_t launch_row_inv(const void* in, float2* out, int nx, int ny, int mx, i
         case 0:
             return launch_row_inv_t<OutStrided, StF32>(in, o, nx, ny, mx, batch, in_plane,
                                                        st.out_scale, st.dyn_inv, tw, s,
-                                                       st.row_form);
+                                                       st.row_form, st.layout);
         case 1:
             return launch_row_inv_t<OutStrided, StF16>(in, o, nx, ny, mx, batch, in_plane,
                                                        st.out_scale, st.dyn_inv, tw, s,
-                                                       st.row_form);
+                                                       st.row_form, st.layout);
         case 2:
             return launch_row_inv_t<OutStrided, StBF16>(in, o, nx, ny, mx, batch, in_plane,
                                                         st.out_scale, st.dyn_inv, tw, s,
-                                                       st.row_form);
+                                                        st.row_form, st.layout);
     }
     return hipErrorInvalidValue;
 }

@@ -108,24 +108,28 @@ struct ShiftedFast {
 
 template <class HF>
 static hipError_t launch_shifted_t(float2* buf, int ny, int my, int mx, const HF& hf,
-                                   const float2* tw, hipStream_t s) {
+                                   const float2* tw, hipStream_t s, int layout) {
     const bool half = (my == 2 * ny);
+    if (layout == 1 && (!half || mx % kTileW != 0)) return hipErrorInvalidValue;
     CWO_DISPATCH_M(my, {
         using C = ColCfg<MM>;
         const int items = (mx + C::COLS - 1) / C::COLS;
-        if (half)
-            hipLaunchKernelGGL((k_col<MM, true, HF, StF32>), dim3(items), dim3(C::THREADS), 0, s,
-                               buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw);
+        if (half && layout == 1)
+            hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayTile>), dim3(items), dim3(C::THREADS),
+                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayTile{ny});
+        else if (half)
+            hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayRow>), dim3(items), dim3(C::THREADS),
+                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayRow{mx});
         else
-            hipLaunchKernelGGL((k_col<MM, false, HF, StF32>), dim3(items), dim3(C::THREADS), 0, s,
-                               buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw);
+            hipLaunchKernelGGL((k_col<MM, false, HF, StF32, LayRow>), dim3(items), dim3(C::THREADS),
+                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayRow{mx});
     });
     return hipGetLastError();
 }
 
 hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const AsmScalars& a,
                                   const AsmShift& sh, float* masks, const float2* tw,
-                                  hipStream_t s) {
+                                  hipStream_t s, int layout) {
     hipLaunchKernelGGL(k_band_masks, dim3((mx + my + 255) / 256), dim3(256), 0, s, masks, mx, my,
                        a.dfx, a.dfy, sh);
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
@@ -144,10 +148,10 @@ hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const Asm
         hf.mask = masks;
         hf.mx = mx;
         hf.my = my;
-        return launch_shifted_t(buf, ny, my, mx, hf, tw, s);
+        return launch_shifted_t(buf, ny, my, mx, hf, tw, s, layout);
     }
     ShiftedH<AsmH> hf{AsmH{a.dfx, a.dfy, a.lam, a.zl, mx, my}, a.dfx, a.dfy, sh, masks, mx, my};
-    return launch_shifted_t(buf, ny, my, mx, hf, tw, s);
+    return launch_shifted_t(buf, ny, my, mx, hf, tw, s, layout);
 }
 
 }  // namespace cwo

@@ -109,7 +109,7 @@ class SFresnel(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """cwo_tuning: the schedule picked by cwo_autotune."""
     _fields_ = [("row_form", ctypes.c_int32), ("zchunk", ctypes.c_int32),
-                ("us_per_plane", ctypes.c_float)]
+                ("us_per_plane", ctypes.c_float), ("layout", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -155,6 +155,8 @@ SIGNATURES = {
     "cwo_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(Tuning)]),
+    "cwo_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
+                                        ctypes.POINTER(Tuning)]),
     "cwo_zstack": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Params),
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -482,7 +484,7 @@ class Context:
     def autotune(self, u, nz=1, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, kind="asm",
                  precision="f32", nopad=False, stream=None):
         """Pick and keep the fastest schedule for this parameter set (cwo_autotune);
-        returns (row_form, zchunk, us_per_plane)."""
+        returns (row_form, zchunk, us_per_plane, layout)."""
         import torch
         u = self._field(u)
         ny, nx = u.shape
@@ -495,7 +497,18 @@ class Context:
                                     self._stream(u, stream), ctypes.byref(t))
         if st != CWO_OK:
             raise CwoError(st, "cwo_autotune")
-        return t.row_form, t.zchunk, t.us_per_plane
+        return t.row_form, t.zchunk, t.us_per_plane, t.layout
+
+    def set_tuning(self, nx, ny, nz=1, kind="asm", precision="f32", nopad=False, row_form=0,
+                   zchunk=0, layout=0, clear=False):
+        """Install a schedule for this parameter set (cwo_set_tuning), or remove it."""
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        p = make_params(nx, ny, 10e-6, None, 633e-9, 0.1, k, precision, nopad)
+        t = Tuning(int(row_form), int(zchunk), 0.0, int(layout))
+        st = self._lib.cwo_set_tuning(self.handle, ctypes.byref(p), int(nz),
+                                      None if clear else ctypes.byref(t))
+        if st != CWO_OK:
+            raise CwoError(st, "cwo_set_tuning")
 
     def zstack(self, u, z, dx=10e-6, dy=None, wavelength=633e-9, kind="asm", precision="f32",
                nopad=False, out=None, stream=None, fresnel_tf=False):

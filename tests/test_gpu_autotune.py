@@ -32,13 +32,77 @@ def test_autotune_single_plane(ctx, n, kind):
     fn = ctx.asm if kind == "asm" else ctx.fresnel
     before = fn(u, 8e-6, 8e-6, 532e-9, 0.3)
     torch.cuda.synchronize()
-    form, zchunk, us = ctx.autotune(u, 1, 8e-6, 8e-6, 532e-9, 0.3, kind=kind)
-    note("autotune %s %d: row_form=%d zchunk=%d %.1f us/plane" % (kind, n, form, zchunk, us))
+    form, zchunk, us, layout = ctx.autotune(u, 1, 8e-6, 8e-6, 532e-9, 0.3, kind=kind)
+    note("autotune %s %d: row_form=%d zchunk=%d layout=%d %.1f us/plane"
+         % (kind, n, form, zchunk, layout, us))
     assert zchunk == 0 and us > 0
-    assert form in ((1, 2) if n >= 512 else (0,))
+    if n >= 1024:   # padded rows of 2048 or more: row-major (two row forms) or tiled
+        assert (layout, form) in ((1, 1), (1, 2), (2, 0))
+    else:
+        assert layout == 0 and form in ((1, 2) if n >= 512 else (0,))
     after = fn(u, 8e-6, 8e-6, 532e-9, 0.3)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
+
+
+@pytest.mark.parametrize("n,kind", [(2048, "asm"), (1024, "fresnel"), (2048, "fresnel")])
+def test_every_schedule_gives_the_default_result(ctx, n, kind):
+    """Every candidate schedule of a single plane (row-major with each row-pass form, tiled),
+    installed with cwo_set_tuning, gives the default schedule's result: the schedules move the
+    same arithmetic through different layouts and launch shapes (bit for bit here; the bar is
+    1e-6 relative)."""
+    import numpy as np
+    import torch
+    from oracle import diffraction as D
+    u = torch.from_numpy(W.uniform_random_field(n, 160 + n)).cuda()
+    fn = ctx.asm if kind == "asm" else ctx.fresnel
+    ctx.set_tuning(n, n, kind=kind, clear=True)
+    ref = fn(u, 8e-6, 8e-6, 532e-9, 0.4)
+    torch.cuda.synchronize()
+    ref_np = ref.cpu().numpy().astype(np.complex128)
+    for layout, form in ((1, 1), (1, 2), (2, 0)):
+        ctx.set_tuning(n, n, kind=kind, row_form=form, layout=layout)
+        y = fn(u, 8e-6, 8e-6, 532e-9, 0.4)
+        torch.cuda.synchronize()
+        err = D.rel_l2(y.cpu().numpy(), ref_np)
+        note("%s %d layout=%d row_form=%d: rel_l2 vs default %.2e, equal %s"
+             % (kind, n, layout, form, err, torch.equal(y, ref)))
+        assert err <= 1e-6
+    ctx.set_tuning(n, n, kind=kind, clear=True)
+
+
+def test_tune_cache_round_trip(tmp_path, monkeypatch):
+    """CWO_TUNE_CACHE: an autotuned schedule is written to the file and a new context loads
+    it (installed schedules are what later calls use)."""
+    import json
+    import torch
+    from paper_1107_5578_amd import cwo
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("CWO_TUNE_CACHE", str(path))
+    u = torch.from_numpy(W.uniform_random_field(1024, 7)).cuda()
+    c1 = cwo.Context(0)
+    try:
+        form, zchunk, us, layout = c1.autotune(u, 1, 8e-6, 8e-6, 532e-9, 0.2)
+    finally:
+        c1.close()
+    entries = json.loads(path.read_text())
+    mine = [e for e in entries if e["nx"] == 1024 and e["nz"] == 1 and e["kind"] == cwo.ANGULAR]
+    assert len(mine) == 1
+    assert (mine[0]["row_form"], mine[0]["zchunk"], mine[0]["layout"]) == (form, zchunk, layout)
+    # a second context reads the file: a forced schedule written there is used and kept
+    mine[0]["layout"], mine[0]["row_form"] = 1, 2
+    path.write_text("[\n" + ",\n".join(" " + json.dumps(e) for e in entries) + "\n]\n")
+    c2 = cwo.Context(0)
+    try:
+        # autotuning another parameter set rewrites the file with both schedules
+        c2.autotune(torch.from_numpy(W.uniform_random_field(256, 8)).cuda(), 1, 8e-6, 8e-6,
+                    532e-9, 0.2)
+    finally:
+        c2.close()
+    entries = json.loads(path.read_text())
+    kept = [e for e in entries if e["nx"] == 1024 and e["nz"] == 1 and e["kind"] == cwo.ANGULAR]
+    assert (kept[0]["layout"], kept[0]["row_form"]) == (1, 2)
+    assert any(e["nx"] == 256 for e in entries)
 
 
 def test_autotune_zstack(ctx):
@@ -48,7 +112,7 @@ def test_autotune_zstack(ctx):
     zs = list(W.zstack_distances(64, 0.05, 0.2))
     before = ctx.zstack(u, zs, cfg.pitch, cfg.pitch, cfg.wavelength)
     torch.cuda.synchronize()
-    form, zchunk, us = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, 0.1)
+    form, zchunk, us, _ = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, 0.1)
     note("autotune zstack 1024x64: row_form=%d zchunk=%d %.1f us/plane" % (form, zchunk, us))
     assert zchunk in (2, 4, 8, 16, 32, 64) and form in (1, 2)
     after = ctx.zstack(u, zs, cfg.pitch, cfg.pitch, cfg.wavelength)

@@ -201,6 +201,47 @@ def test_batch_independent_fields(ctx, n, kind):
                                              0.07), "batched field 3")
 
 
+@pytest.mark.parametrize("n", [256, 2048])
+def test_batch_mixed_parameters_one_launch_per_pass(ctx, n):
+    """Jobs of one geometry on different fields with different distances, wavelengths and
+    kinds run as one batch: one launch for each row pass and one column launch per
+    transfer-function form present (the library's own launch counts), every plane equal to
+    its single call bit for bit, and planes of each kind against the FP64 oracle (ASM and
+    Fresnel, near and far, negative z)."""
+    import torch
+    from paper_1107_5578_amd import cwo
+    note("mixed-parameter batch %d^2" % n)
+    rng = np.random.default_rng(91)
+    specs = []
+    for k in range(9):
+        kind = "asm" if k % 3 != 1 else "fresnel"
+        z = float(rng.uniform(0.02, 0.9)) * (-1.0 if k == 5 else 1.0)
+        lam = float((473e-9, 532e-9, 633e-9)[k % 3])
+        specs.append((kind, dict(dx=8e-6, dy=8e-6, wavelength=lam, z=z)))
+    fields = [torch.from_numpy(W.uniform_random_field(n, 900 + k)).cuda() for k in range(len(specs))]
+    outs = [torch.empty_like(f) for f in fields]
+    ctx.batch([(kind, f, o, kw) for (kind, kw), f, o in zip(specs, fields, outs)])
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.batch([(kind, f, o, kw) for (kind, kw), f, o in zip(specs, fields, outs)])
+    counts = {st: ctx.profile_read(st)[1] for st in (cwo.STAGE_ROW_FWD, cwo.STAGE_COL,
+                                                      cwo.STAGE_ROW_INV)}
+    ctx.profile(False)
+    # ASM planes of one series length plus Fresnel planes: two column launches (at most three)
+    assert counts[cwo.STAGE_ROW_FWD] == 1 and counts[cwo.STAGE_ROW_INV] == 1, counts
+    assert 2 <= counts[cwo.STAGE_COL] <= 3, counts
+    for (kind, kw), f, o in zip(specs, fields, outs):
+        one = (ctx.asm if kind == "asm" else ctx.fresnel)(f, kw["dx"], kw["dy"], kw["wavelength"],
+                                                          kw["z"])
+        torch.cuda.synchronize()
+        assert torch.equal(o, one), (kind, kw)
+    for k in (0, 1, 5):
+        kind, kw = specs[k]
+        ref = D.propagate(fields[k].cpu().numpy(), kind, kw["dx"], kw["dy"], kw["wavelength"],
+                          kw["z"])
+        check(outs[k].cpu().numpy(), ref, "mixed batch plane %d (%s)" % (k, kind))
+
+
 def test_batch_chained_jobs_keep_their_order(ctx):
     # a job that reads another job's output is not batched with it
     import torch
