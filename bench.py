@@ -542,10 +542,20 @@ def main():
             torch.cuda.synchronize()
             gms = a.elapsed_time(b)
             e = errs.cpu().numpy()
+            # per-kernel times of 20 more iterations (library HIP events on the stream)
+            ctx.profile(True)
+            ctx.gs(tp, ta1, ta2, g.pitch, g.pitch, g.wavelength, g.z, iterations=20,
+                   precision=prec)
+            stages = {}
+            for st in (cwo.STAGE_COL, cwo.STAGE_ROW_GS):
+                ms, cnt = ctx.profile_read(st)
+                stages[cwo.STAGE_NAMES[st]] = round(1000.0 * ms / max(cnt, 1), 2)
+            ctx.profile(False)
             gs[prec + "_storage"] = {
                 "ms_total": round(gms, 3), "ms_per_iteration": round(gms / 200, 4),
                 "propagations_per_s": round(400 * 1000.0 / gms, 1),
-                "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1])}
+                "E_0": float("%.5f" % e[0]), "E_199": float("%.5f" % e[-1]),
+                "kernel_us_with_events": stages}
             del tp
         del ta1, ta2, tu
 

@@ -968,6 +968,33 @@ size_t held_bytes(cwo_ctx* c) {
     return h;
 }
 
+// Requests of one serving batch that do not touch each other's buffers are independent;
+// such a batch is reordered (stably) so that requests of one geometry sit next to each
+// other, those on one field first among them: run_jobs then runs them as shared-launch
+// batches or z-stacks. A batch with a dependence keeps its arrival order.
+void group_batch(std::vector<cwo_job>& batch, std::vector<uint64_t>& ids) {
+    const size_t n = batch.size();
+    for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j < n; ++j)
+            if (i != j && (batch[i].out == batch[j].in || batch[i].out == batch[j].out)) return;
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    auto key = [&](size_t i) {
+        const cwo_params& p = batch[i].p;
+        return std::make_tuple(p.nx, p.ny, p.dx, p.dy, p.flags, p.precision,
+                               reinterpret_cast<uintptr_t>(batch[i].in));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key(a) < key(b); });
+    std::vector<cwo_job> jb(n);
+    std::vector<uint64_t> ib(n);
+    for (size_t i = 0; i < n; ++i) {
+        jb[i] = batch[order[i]];
+        ib[i] = ids[order[i]];
+    }
+    batch.swap(jb);
+    ids.swap(ib);
+}
+
 void serve_loop(cwo_ctx* c) {
     (void)hipSetDevice(c->device);
     std::unique_lock<std::mutex> lk(c->qmu);
@@ -1007,7 +1034,11 @@ void serve_loop(cwo_ctx* c) {
                 const uint64_t id = c->queue[k];
                 const Ticket& tk = c->tickets[id];
                 batch.push_back(tk.job);
-                const WsNeed need = jobs_need(c, batch.data(), (int)batch.size());
+                // the memory of the batch as it will run (grouped by geometry)
+                std::vector<cwo_job> grouped = batch;
+                std::vector<uint64_t> gids(batch.size(), 0);
+                group_batch(grouped, gids);
+                const WsNeed need = jobs_need(c, grouped.data(), (int)grouped.size());
                 auto fits = [&] {
                     return !c->budget || c->reserved + io + io_bytes(&tk.job.p) + held_bytes(c) +
                                                  growth(sl.ws, need) <=
@@ -1048,6 +1079,7 @@ void serve_loop(cwo_ctx* c) {
                 break;
             }
             for (size_t k = 0; k < ids.size(); ++k) c->queue.pop_front();
+            group_batch(batch, ids);
             const double t = now_s(c);
             std::vector<hipEvent_t> waits;
             for (uint64_t id : ids) {
