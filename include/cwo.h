@@ -245,8 +245,10 @@ typedef struct {
     int32_t zchunk;       /* planes per z-stack launch (0: single-plane calls) */
     float us_per_plane;   /* the best measured time */
     int32_t layout;       /* padded plane between the passes: 1 row-major, 2 tiled (four
-                             columns per tile, two rows per row-pass group), 0 the default
-                             choice (tiled for 2048 <= 2nx <= 4096) */
+                             columns per tile, two rows per row-pass group; rows and
+                             columns of 8192 as two transforms of 4096), 0 the default
+                             choice (tiled for 2048 <= 2nx <= 8192; the Gerchberg-Saxton
+                             loop keeps rows of 8192 row-major) */
 } cwo_tuning;
 
 /* Autotuner: runs the candidate schedules of this parameter set (for single planes the

@@ -16,8 +16,16 @@ static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, siz
         using C = ColCfg<MM>;
         const int items = (mx + C::COLS - 1) / C::COLS * batch;
         if (half && layout == 1) {
-            hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items), dim3(C::THREADS), 0,
-                               s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw, LayTile{ny});
+            if constexpr (MM == 8192) {
+                // padded columns of length 8192 as two transforms of 4096, one per block
+                hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx * batch),
+                                   dim3(MM / 32), 0, s, (SE*)buf, ny, mx, batch, plane, hf, hscale,
+                                   tw, LayTile{ny});
+            } else {
+                hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items), dim3(C::THREADS),
+                                   0, s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw,
+                                   LayTile{ny});
+            }
         } else if (half) {
             hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS), 0,
                                s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw, LayRow{mx});

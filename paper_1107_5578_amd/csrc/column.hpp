@@ -167,7 +167,9 @@ constexpr bool rows_early() {
 // inverse FFT, in place; one (plane, column tile) item per block. LAY addresses the
 // plane (row-major or tiled). With HALF the rows Ny..My-1 of the padded column are zero:
 // they are neither loaded nor added in the first forward pass, and only rows < Ny of the
-// result are computed to the end and stored.
+// result are computed to the end and stored. hscale (a power of two, 1 for complex64
+// storage) multiplies the stored values; scaling by a power of two commutes exactly with
+// the inverse transform, so this equals scaling the transfer function.
 template <int M, bool HALF, class HF, class ST, class LAY>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_col(typename ST::E* __restrict__ buf,
                                                               int ny, int mx, int batch,
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     const int it = xcd_remap(blockIdx.x, gridDim.x);
     const int pl = it / ntiles, tile = it - pl * ntiles;
     const int col0 = (tile * C::PAIRS + pair) * P;  // first column of this thread (mx is even)
-    const bool active = col0 < mx;                  // tiles may overhang narrow planes
+    // tiles of several pairs may overhang narrow planes (a one-pair tile never does)
+    const bool active = C::PAIRS == 1 || col0 < mx;
     const int col = active ? col0 : 0;
     SE* base = buf + buffer_plane(hf, pl) * plane;
     const auto& hfp = plane_tf(hf, pl);  // this block's transfer function
@@ -226,11 +229,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
         if constexpr (EARLY) hr = hre[r];
         else hr = hfp.row(j + r * T);
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            float2 h = hfp(hc[p], hr);
-            if (hscale != 1.0f) h = make_float2(h.x * hscale, h.y * hscale);
-            v[p][r] = cmul(v[p][r], h);
-        }
+        for (int p = 0; p < P; ++p) v[p][r] = cmul(v[p][r], hfp(hc[p], hr));
     }
     fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
 #pragma unroll
@@ -240,9 +239,65 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
         if (st) {
             PK t;
 #pragma unroll
-            for (int p = 0; p < P; ++p) t.e[p] = ST::enc(v[p][r]);
+            for (int p = 0; p < P; ++p) t.e[p] = ST::enc(make_float2(v[p][r].x * hscale, v[p][r].y * hscale));
             *reinterpret_cast<PK*>(base + lay.at(y, col)) = t;
         }
+    }
+}
+
+// Column pass for padded columns of length M = 2*MH with MH non-zero rows, as two
+// transforms of length MH. With W = exp(-2 pi i/M), the padded forward transform's even
+// bins are DFT_MH(x)[k] and its odd bins DFT_MH(x_n W^n)[k]; after multiplying by H(2k) and
+// H(2k+1), the first MH outputs of the padded inverse transform are
+// IDFT_MH(even)[n] + W^-n IDFT_MH(odd)[n]. One column per block of T = MH/16 threads, the
+// two length-MH transforms sharing each thread's twiddles and 16-byte LDS slots (the pair
+// of the two-column kernel), so a block needs half the threads and LDS of the length-M
+// kernel and two blocks fit a CU. twm: the length-M table (the length-MH twiddles are its
+// even entries).
+template <int MH, class HF, class ST, class LAY>
+__global__ __launch_bounds__(MH / 16) __attribute__((amdgpu_waves_per_eu(2))) void k_col_split(
+    typename ST::E* __restrict__ buf, int ny, int mx, int batch, size_t plane, HF hf, float hscale,
+    const float2* __restrict__ twm, LAY lay) {
+    constexpr int E = 16, T = MH / E, P = 2;
+    using SE = typename ST::E;
+    __shared__ float4 lds4[lds_elems<MH>()];
+    float2* lds = reinterpret_cast<float2*>(lds4);
+    const int j = threadIdx.x;
+    TwCache<MH, E> twc;
+    twc.load(j, twm, 2);
+    const int it = xcd_remap(blockIdx.x, gridDim.x);
+    const int pl = it / mx, col = it - pl * mx;
+    SE* base = buf + buffer_plane(hf, pl) * plane;
+    const auto& hfp = plane_tf(hf, pl);
+    using PH = std::decay_t<decltype(hfp)>;
+    float2 v[P][E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int n = j + r * T;
+        const float2 x = ST::dec(base[lay.at(n, col)]);
+        v[0][r] = x;
+        v[1][r] = cmul(x, twm[n]);
+    }
+    const typename PH::Col hc = hfp.column(col);
+    fft<MH, E, P, FWD>(v, lds, j, twc);
+    // opaque copies of j: the transfer function and the twiddles of the last step are
+    // computed where they are used rather than held in registers through the transforms
+    int jh = j;
+    asm volatile("" : "+v"(jh));
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int k = jh + r * T;
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[p][r] = cmul(v[p][r], hfp(hc, hfp.row(2 * k + p)));
+    }
+    fft<MH, E, P, INV>(v, lds, j, twc);
+    int jj = j;
+    asm volatile("" : "+v"(jj));
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int n = jj + r * T;
+        const float2 o = cadd(v[0][r], ctw<INV>(v[1][r], twm[n]));
+        base[lay.at(n, col)] = ST::enc(make_float2(o.x * hscale, o.y * hscale));
     }
 }
 

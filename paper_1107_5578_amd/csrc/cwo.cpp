@@ -440,7 +440,7 @@ cwo_tuning tuned_for(cwo_ctx* c, const cwo_params* p, int kind, int nz) {
 }
 
 // Whether the tiled plane can be used for this geometry at all (padded planes of
-// 2048 <= Mx <= 8192; the default rule takes it up to 4096).
+// 2048 <= Mx <= 8192, as the default rule).
 bool tiles_possible(const Geometry& g) {
     return g.mx == 2 * g.nx && g.my == 2 * g.ny && g.mx >= 2048 && g.mx <= 8192;
 }
@@ -1808,7 +1808,8 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     cwo::GsScale g2, g1;  // row passes after the +z and the -z column pass
     sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
     g2.scale = g1.scale = sto.out_scale;
-    sto.layout = g2.layout = g1.layout = cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
+    // (the fused ping-pong row kernel has no split form: rows of 8192 stay row-major)
+    sto.layout = g2.layout = g1.layout = cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) && g.mx <= 4096 ? 1 : 0;
     if (p->precision != CWO_PREC_F32) {
         sto.prec = g2.prec = g1.prec = p->precision == CWO_PREC_F16_STORAGE ? 1 : 2;
         const int kx = ilog2(g.mx) / 2;

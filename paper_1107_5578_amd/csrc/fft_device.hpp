@@ -85,7 +85,8 @@ __device__ __forceinline__ float2 wconst(float2 a) {
             constexpr float c = (oct == 1 || oct == 7) ? h : -h;
             constexpr float s0 = (oct == 1 || oct == 3) ? h : -h;  // sin(oct*pi/4)
             constexpr float s = (DIR == FWD) ? -s0 : s0;
-            return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+            // fused as in the general case, so that every kernel rounds it alike
+            return make_float2(__fmaf_rn(c, a.x, -s * a.y), __fmaf_rn(c, a.y, s * a.x));
         }
     } else {
         // general angle 2*pi*m/R with R <= 32: cos/sin of multiples of pi/16
@@ -224,7 +225,8 @@ template <int M, int E>
 struct TwCache {
     using PL = Plan<M, E>;
     float2 w[PL::PASSES][E];
-    __device__ __forceinline__ void load(int j, const float2* __restrict__ tw) {
+    // tw[k] = exp(-2 pi i k / M); with stride s the table is of length s*M (every s-th entry)
+    __device__ __forceinline__ void load(int j, const float2* __restrict__ tw, int stride = 1) {
         constexpr int T = PL::T;
         [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
             (([&] {
@@ -238,7 +240,7 @@ struct TwCache {
                      for (int i = 0; i < NB; ++i) {
                          const int k = (j + i * T) & (NS - 1);
 #pragma unroll
-                         for (int kk = 1; kk < RP; ++kk) w[p][i * RP + kk] = tw[k * kk * STEP];
+                         for (int kk = 1; kk < RP; ++kk) w[p][i * RP + kk] = tw[stride * (k * kk * STEP)];
                      }
                  }
              }()),

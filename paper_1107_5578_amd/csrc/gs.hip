@@ -14,6 +14,32 @@ namespace cwo {
 // and the constrained field by fwd_scale * (*dyn_fwd) before the forward transform (null
 // dyn pointers count as 1), so FP16 storage stays in range.
 
+// Sum of one double per thread over the T threads of a row (T a power of two; the row's
+// threads are T consecutive lanes, or whole wavefronts when T >= 64): a butterfly of
+// cross-lane exchanges within the wavefront, then the wavefront partials added in wavefront
+// order by the row's first thread. The order is fixed, so the sum is deterministic. red:
+// T/64 doubles of LDS for the row. All threads of the block call it (block barriers).
+template <int T>
+__device__ __forceinline__ double row_sum(double x, double* red, int j) {
+    constexpr int W = T < 64 ? T : 64;
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if constexpr (T <= 64) {
+        return x;
+    } else {
+        lds_barrier();
+        if ((j & 63) == 0) red[j >> 6] = x;
+        lds_barrier();
+        double t = 0.0;
+        if (j == 0) {
+#pragma unroll
+            for (int i = 0; i < T / 64; ++i) t += red[i];
+        }
+        lds_barrier();
+        return t;
+    }
+}
+
 template <int M, bool HALF, class ST>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
     typename ST::E* __restrict__ spec, const float* __restrict__ amp, float2* __restrict__ out,
@@ -64,17 +90,8 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
         }
     }
     if (num) {
-        // deterministic per-row sum: lane partials through LDS, summed in index order
-        double* red = reinterpret_cast<double*>(my_lds);
-        lds_barrier();
-        red[j] = acc;
-        lds_barrier();
-        if (j == 0 && valid) {
-            double t = 0.0;
-            for (int i = 0; i < T; ++i) t += red[i];
-            num[row] = t;
-        }
-        lds_barrier();
+        const double t = row_sum<T>(acc, reinterpret_cast<double*>(my_lds), j);
+        if (j == 0 && valid) num[row] = t;
     }
     if (out) {
         if (valid) {
@@ -127,23 +144,39 @@ __global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
     const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, groups);
     TwCache<M, E> twc;
     twc.load(j, tw);
-    auto load = [&](int g, PK (&d)[K::CPT]) {
+    auto load = [&](int g, PK (&d)[K::CPT], int tl) {
         const int y0 = g * C::RPB;
 #pragma unroll
         for (int k = 0; k < K::CPT; ++k) {
-            const int c = tid + k * C::THREADS;
+            const int c = tl + k * C::THREADS;
             const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
             d[k] = *reinterpret_cast<const PK*>(spec + ((size_t)t * ny + y0) * kTileW + q * K::CE);
         }
     };
-    PK cur[K::CPT], nxt[K::CPT];
+    // the amplitudes of the thread's row are loaded with the group's tile rows
+    auto load_amp = [&](int g, float (&d)[NL], int jl) {
+        const float* arow = amp + (size_t)(g * C::RPB + sub) * nx;
+#pragma unroll
+        for (int r = 0; r < NL; ++r) d[r] = arow[jl + r * T];
+    };
+    // one buffer each: a group's tile rows are in LDS (and its amplitudes in v's
+    // constraint) before the next group's loads into the same registers are issued
+    PK cur[K::CPT];
+    float acur[NL];
     int g = ir.first;
-    if (g < ir.end) load(g, cur);
-    for (; g < ir.end; g += ir.step) {
+    if (g >= ir.end) return;  // the whole block (ir is uniform)
+    load(g, cur, tid);
+    load_amp(g, acur, j);
+    for (;;) {
+        const bool more = g + ir.step < ir.end;
+        // the thread's indices, opaque to the compiler in each iteration: the addresses
+        // derived from them are recomputed here instead of being held across the loop
+        int jt = j, tt = tid;
+        asm volatile("" : "+v"(jt), "+v"(tt));
         lds_barrier();
 #pragma unroll
         for (int k = 0; k < K::CPT; ++k) {
-            const int c = tid + k * C::THREADS;
+            const int c = tt + k * C::THREADS;
 #pragma unroll
             for (int e = 0; e < K::CE; ++e) lds[c * K::CE + e] = ST::dec(cur[k].e[e]);
         }
@@ -151,19 +184,18 @@ __global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
         float2 v[1][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            const int x = j + r * T;
+            const int x = jt + r * T;
             v[0][r] = lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)];
         }
         lds_barrier();
-        if (g + ir.step < ir.end) load(g + ir.step, nxt);
+        if (more) load(g + ir.step, cur, tt);
         const int y0 = g * C::RPB, row = y0 + sub;
-        const float* arow = amp + (size_t)row * nx;
-        fft<M, E, 1, INV>(v, my_lds, j, twc);
+        fft<M, E, 1, INV>(v, my_lds, jt, twc);
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             if (r < NL) {
-                const float a = arow[j + r * T];
+                const float a = acur[r];
                 const float re = v[0][r].x * scale, im = v[0][r].y * scale;
                 const float m2 = re * re + im * im;
                 float2 c;
@@ -182,40 +214,32 @@ __global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
                 v[0][r] = make_float2(0.f, 0.f);
             }
         }
+        if (more) load_amp(g + ir.step, acur, jt);
         if (num) {
-            // deterministic per-row sum: lane partials through LDS, summed in index order
-            double* red = reinterpret_cast<double*>(my_lds);
-            lds_barrier();
-            red[j] = acc;
-            lds_barrier();
-            if (j == 0) {
-                double t = 0.0;
-                for (int i = 0; i < T; ++i) t += red[i];
-                num[row] = t;
-            }
-            lds_barrier();
+            const double t = row_sum<T>(acc, reinterpret_cast<double*>(my_lds), jt);
+            if (jt == 0) num[row] = t;
         }
         if (out) {
             float2* orow = out + (size_t)row * nx;
 #pragma unroll
-            for (int r = 0; r < NL; ++r) orow[j + r * T] = v[0][r];
+            for (int r = 0; r < NL; ++r) orow[jt + r * T] = v[0][r];
         } else {
             if (fwd_scale != 1.0f) {
 #pragma unroll
                 for (int r = 0; r < E; ++r)
                     v[0][r] = make_float2(v[0][r].x * fwd_scale, v[0][r].y * fwd_scale);
             }
-            fft_zpad<M, E, 1, FWD>(v, my_lds, j, twc);
+            fft_zpad<M, E, 1, FWD>(v, my_lds, jt, twc);
             lds_barrier();
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                const int x = j + r * T;
+                const int x = jt + r * T;
                 lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)] = v[0][r];
             }
             lds_barrier();
 #pragma unroll
             for (int k = 0; k < K::CPT; ++k) {
-                const int c = tid + k * C::THREADS;
+                const int c = tt + k * C::THREADS;
                 const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
                 PK pk;
 #pragma unroll
@@ -223,8 +247,8 @@ __global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
                 *reinterpret_cast<PK*>(spec + ((size_t)t * ny + y0) * kTileW + q * K::CE) = pk;
             }
         }
-#pragma unroll
-        for (int k = 0; k < K::CPT; ++k) cur[k] = nxt[k];
+        if (!more) break;
+        g += ir.step;
     }
 }
 
@@ -275,7 +299,8 @@ hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int 
     if (layout == 1) {
         if (!half) return hipErrorInvalidValue;
         CWO_DISPATCH_M(mx, {
-            if constexpr (MM >= 2048) {
+            // (rows of 8192 stay row-major in this loop: no split form of the fused kernel)
+            if constexpr (MM >= 2048 && MM <= 4096) {
                 using C = TileRowCfg<MM>;
                 auto k = k_row_gs_tile<MM, ST>;
                 hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),

@@ -52,10 +52,10 @@ struct Storage {
 };
 
 // The tiled plane layout is taken for padded planes (Mx = 2Nx, My = 2Ny) with
-// 2048 <= Mx <= 4096 (at Mx = 8192 a block holds one row and its quarter-line tile rows
-// cost more in the row passes than the column pass gains: measured).
+// 2048 <= Mx <= 8192 (at Mx = 8192 the row and column passes take the split form: two
+// transforms of 4096 per row or column).
 inline bool tiled_ok(int nx, int ny, int mx, int my) {
-    return mx == 2 * nx && my == 2 * ny && mx >= 2048 && mx <= 4096;
+    return mx == 2 * nx && my == 2 * ny && mx >= 2048 && mx <= 8192;
 }
 
 constexpr int kRangeBlocks = 1024;

@@ -23,18 +23,11 @@
 //             h_F factorises into two 1-D transforms of chirps, computed here
 //             by FP64 FFTs.
 
-#include "column.hpp"
+#include "rowsplit.hpp"
 
 namespace cwo {
 
 // ---- row forward: zero-pad + FFT --------------------------------------------
-
-// Scaling of the stored planes (powers of two, exact): the field is multiplied by
-// sc.in * (*sc.dyn) before the row transform (sc.dyn: a device-computed factor or null).
-struct RowScale {
-    float in;
-    const float* dyn;
-};
 
 template <int M, bool HALF, class ST, class IN>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_fwd(IN ins,
@@ -373,7 +366,15 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
     if (layout == 1) {
         if (!half) return hipErrorInvalidValue;
         CWO_DISPATCH_M(mx, {
-            if constexpr (MM >= 2048) {
+            if constexpr (MM == 8192) {
+                // two rows per block, the next group's values all loaded during the transform
+                using C = SplitRowCfg<MM / 2, 2>;
+                if ((ny * batch) % C::RPB != 0) return hipErrorInvalidValue;
+                const int groups = ny * batch / C::RPB;
+                auto k = k_row_fwd_tsplit<MM / 2, 2, C::E, false, ST, IN>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
+            } else if constexpr (MM >= 2048) {
                 using C = TileRowCfg<MM>;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_fwd_tile<MM, ST, IN>;
@@ -449,7 +450,21 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
     if (layout == 1) {
         if (!half) return hipErrorInvalidValue;
         CWO_DISPATCH_M(mx, {
-            if constexpr (MM >= 2048) {
+            if constexpr (MM == 8192) {
+                // complex64: two rows per block, 8 of the next group's 16 chunks loaded
+                // during the transform; 16-bit storage: one row per block (two blocks per
+                // CU), 4 of 8 chunks during the transform and the rest after the stores
+                // (measured at 4096^2)
+                constexpr bool F32 = std::is_same_v<ST, StF32>;
+                constexpr int RPB = F32 ? 2 : 1, PF = F32 ? 8 : 4;
+                using C = SplitRowCfg<MM / 2, RPB>;
+                if ((ny * batch) % C::RPB != 0) return hipErrorInvalidValue;
+                const int groups = ny * batch / C::RPB;
+                auto k = k_row_inv_tsplit<MM / 2, RPB, PF, !F32, OUT, ST>;
+                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                                   0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
+                                   dyn_inv, tw);
+            } else if constexpr (MM >= 2048) {
                 using C = TileRowCfg<MM>;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_inv_tile<MM, OUT, ST>;

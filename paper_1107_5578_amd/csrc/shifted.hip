@@ -114,10 +114,15 @@ static hipError_t launch_shifted_t(float2* buf, int ny, int my, int mx, const HF
     CWO_DISPATCH_M(my, {
         using C = ColCfg<MM>;
         const int items = (mx + C::COLS - 1) / C::COLS;
-        if (half && layout == 1)
-            hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayTile>), dim3(items), dim3(C::THREADS),
-                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayTile{ny});
-        else if (half)
+        if (half && layout == 1) {
+            if constexpr (MM == 8192)  // two transforms of 4096 per column, one per block
+                hipLaunchKernelGGL((k_col_split<MM / 2, HF, StF32, LayTile>), dim3(mx), dim3(MM / 32),
+                                   0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayTile{ny});
+            else
+                hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayTile>), dim3(items),
+                                   dim3(C::THREADS), 0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw,
+                                   LayTile{ny});
+        } else if (half)
             hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayRow>), dim3(items), dim3(C::THREADS),
                                0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayRow{mx});
         else

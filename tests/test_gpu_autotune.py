@@ -42,7 +42,14 @@ def test_autotune_single_plane(ctx, n, kind):
         assert layout == 0 and form in ((1, 2) if n >= 512 else (0,))
     after = fn(u, 8e-6, 8e-6, 532e-9, 0.3)
     torch.cuda.synchronize()
-    assert torch.equal(before, after)
+    # the tuned schedule runs other kernels over the same arithmetic: the default result to
+    # the schedules' bar (1e-6 relative), usually bit for bit
+    import numpy as np
+    from oracle import diffraction as D
+    err = D.rel_l2(after.cpu().numpy(), before.cpu().numpy().astype(np.complex128))
+    note("autotune %s %d: rel_l2 vs default %.2e, equal %s"
+         % (kind, n, err, torch.equal(before, after)))
+    assert err <= 1e-6
 
 
 @pytest.mark.parametrize("n,kind", [(2048, "asm"), (1024, "fresnel"), (2048, "fresnel")])

@@ -132,7 +132,7 @@ def test_kinoform_example(ctx):
 @pytest.mark.parametrize("kind,n,prec,nopad", [
     ("asm", 256, "f32", False), ("fresnel", 128, "f32", False), ("asm", 2048, "f32", False),
     ("asm", 64, "f32", True), ("asm", 512, "f16", False), ("fresnel", 1024, "bf16", False),
-    ("asm", 16, "f32", False)])
+    ("asm", 16, "f32", False), ("asm", 4096, "f32", False), ("fresnel", 4096, "f16", False)])
 def test_fused_intensity_equals_propagate_then_intensity(ctx, kind, n, prec, nopad):
     """cwo_asm_intensity / cwo_fresnel_intensity store |u|^2 from the last pass: bit for
     bit the intensity of the complex result of the same propagation, and within the

@@ -182,6 +182,38 @@ def test_max_size_4096(ctx):
     check(y, ref, label="asm-4096")
 
 
+def test_fresnel_4096(ctx):
+    # the 8192-point rows and columns of the tiled plane (two 4096-point transforms each)
+    # with the Fresnel factors
+    u = W.uniform_random_field(4096, 44)
+    note("fresnel 4096")
+    y = gpu_run(ctx, D.FRESNEL, u, 8e-6, 8e-6, 633e-9, 0.3)
+    ref = D.fresnel(u, 8e-6, 8e-6, 633e-9, 0.3)
+    check(y, ref, label="fresnel-4096")
+
+
+@pytest.mark.parametrize("kind", [D.ASM, D.FRESNEL])
+def test_4096_layouts_agree(ctx, kind):
+    """The row-major and the tiled (split-transform) plane at 4096^2 compute the same
+    propagation: both within the oracle's bound, here against each other (the tuned layout
+    is forced through the library's tuning entry)."""
+    import torch
+    u = torch.from_numpy(W.uniform_random_field(4096, 45)).cuda()
+    note("layouts agree 4096 %s" % kind)
+    prop = ctx.asm if kind == D.ASM else ctx.fresnel
+    args = (8e-6, 8e-6, 532e-9, 0.4)
+    ys = []
+    try:
+        for layout in (1, 2):
+            ctx.set_tuning(4096, 4096, kind=kind, layout=layout)
+            ys.append(prop(u, *args).cpu().numpy().astype(np.complex128))
+    finally:
+        ctx.set_tuning(4096, 4096, kind=kind, clear=True)
+    peak = np.abs(ys[0]).max()
+    assert np.abs(ys[1] - ys[0]).max() <= 2 * ELEM * peak
+    assert D.rel_l2(ys[1], ys[0]) <= 2 * REL_L2
+
+
 def test_invalid_calls_raise(ctx):
     import torch
     from paper_1107_5578_amd import cwo

@@ -84,6 +84,21 @@ def test_shifted_2048_band_limited(ctx):
     check(y.cpu().numpy(), ref, "shifted 2048")
 
 
+def test_shifted_4096(ctx):
+    # padded columns of 8192 on the tiled plane: the split column pass with the shifted,
+    # band-limited transfer function
+    import torch
+    u = W.uniform_random_field(4096, 47)
+    z = 2.0
+    wx = S.band_limit(4096, 8e-6, 532e-9, z)
+    note("shifted 4096 z=%g band=%g" % (z, wx))
+    t = torch.from_numpy(u).cuda()
+    y = ctx.asm_shifted(t, 8e-6, 8e-6, 532e-9, z, 0.8e-3, 0.5e-3, 0.0, wx, 0.0, wx)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, 8e-6, 8e-6, 532e-9, z, 0.8e-3, 0.5e-3, 0.0, wx, 0.0, wx)
+    check(y.cpu().numpy(), ref, "shifted 4096")
+
+
 def test_exact_phase_path_with_shift(ctx):
     # 0.6 um pitch: s > 0.05 selects the FP64 per-bin form, evanescent corners included
     import torch

@@ -242,6 +242,33 @@ def test_batch_mixed_parameters_one_launch_per_pass(ctx, n):
         check(outs[k].cpu().numpy(), ref, "mixed batch plane %d (%s)" % (k, kind))
 
 
+def test_batch_mixed_parameters_4096(ctx):
+    """A mixed batch at 4096^2 (tiled plane, split transforms): one launch per row pass,
+    every plane equal to its single call bit for bit, the Fresnel plane against the oracle."""
+    import torch
+    from paper_1107_5578_amd import cwo
+    note("mixed-parameter batch 4096^2")
+    specs = [("asm", dict(dx=8e-6, dy=8e-6, wavelength=473e-9, z=0.6)),
+             ("fresnel", dict(dx=8e-6, dy=8e-6, wavelength=532e-9, z=0.35)),
+             ("asm", dict(dx=8e-6, dy=8e-6, wavelength=633e-9, z=-0.2))]
+    fields = [torch.from_numpy(W.uniform_random_field(4096, 940 + k)).cuda()
+              for k in range(len(specs))]
+    outs = [torch.empty_like(f) for f in fields]
+    ctx.profile(True)
+    ctx.batch([(kind, f, o, kw) for (kind, kw), f, o in zip(specs, fields, outs)])
+    counts = {st: ctx.profile_read(st)[1] for st in (cwo.STAGE_ROW_FWD, cwo.STAGE_ROW_INV)}
+    ctx.profile(False)
+    assert counts[cwo.STAGE_ROW_FWD] == 1 and counts[cwo.STAGE_ROW_INV] == 1, counts
+    for (kind, kw), f, o in zip(specs, fields, outs):
+        one = (ctx.asm if kind == "asm" else ctx.fresnel)(f, kw["dx"], kw["dy"], kw["wavelength"],
+                                                          kw["z"])
+        torch.cuda.synchronize()
+        assert torch.equal(o, one), (kind, kw)
+    kind, kw = specs[1]
+    ref = D.propagate(fields[1].cpu().numpy(), kind, kw["dx"], kw["dy"], kw["wavelength"], kw["z"])
+    check(outs[1].cpu().numpy(), ref, "mixed batch 4096 plane 1 (fresnel)")
+
+
 def test_batch_chained_jobs_keep_their_order(ctx):
     # a job that reads another job's output is not batched with it
     import torch
