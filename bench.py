@@ -43,7 +43,8 @@ def kernel_source_hash() -> str:
     for rel in ("paper_1107_5578_amd/csrc/plane.hip", "paper_1107_5578_amd/csrc/column.hip",
                 "paper_1107_5578_amd/csrc/column.hpp",
                 "paper_1107_5578_amd/csrc/kernel_common.hpp",
-                "paper_1107_5578_amd/csrc/fft_device.hpp", "paper_1107_5578_amd/csrc/launch.hpp"):
+                "paper_1107_5578_amd/csrc/fft_device.hpp", "paper_1107_5578_amd/csrc/launch.hpp",
+                "paper_1107_5578_amd/csrc/rowsplit.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
