@@ -446,7 +446,7 @@ def main():
         # batched form: the same field to 64 distances in one cwo_zstack call, against the
         # same 64 distances as 64 plain calls (the plain figure above is one distance)
         zs = list(W.zstack_distances(64, 0.05, 0.5))
-        z_form, z_chunk, _, _ = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
+        z_form, z_chunk, _, _, _ = ctx.autotune(u, 64, cfg.pitch, cfg.pitch, cfg.wavelength, cfg.z)
         z_pps, z_ms = time_zstack(ctx, torch, u, zs, cfg.pitch, cfg.wavelength, 5, 2)
         batched = {"form": "cwo_zstack, one %dx%d field to 64 distances in [0.05, 0.5] m" % (n, n),
                    "planes_per_s": round(z_pps, 1), "ms_per_stack": round(z_ms, 4),
@@ -456,7 +456,7 @@ def main():
         u3 = torch.from_numpy(W.field_for(c3)).to(dev)
         z3 = list(W.zstack_distances(64, 0.05, 0.2))
         # the library's autotuner picks the row-pass form and the chunk size for this stack
-        form, zchunk, _, _ = ctx.autotune(u3, 64, c3.pitch, c3.pitch, c3.wavelength, 0.1)
+        form, zchunk, _, _, _ = ctx.autotune(u3, 64, c3.pitch, c3.pitch, c3.wavelength, 0.1)
         c3_pps, c3_ms = time_zstack(ctx, torch, u3, z3, c3.pitch, c3.wavelength, 10, 2)
         batched["zstack_1024x64"] = {"planes_per_s": round(c3_pps, 1), "ms_per_stack": round(c3_ms, 4),
                                      "schedule": {"row_form": form, "zchunk": zchunk},

@@ -249,12 +249,17 @@ typedef struct {
                              columns of 8192 as two transforms of 4096), 0 the default
                              choice (tiled for 2048 <= 2nx <= 8192; the Gerchberg-Saxton
                              loop keeps rows of 8192 row-major) */
+    int32_t col_form;     /* column pass on the tiled plane, padded columns of 4096 or 8192:
+                             1 two adjacent columns per thread, one transform of the full
+                             length each; 2 each column as two transforms of half the
+                             length (the even and the odd bins), one column per block; 0 the
+                             default choice (2 at 8192, 1 at 4096); other planes: 0 only */
 } cwo_tuning;
 
 /* Autotuner: runs the candidate schedules of this parameter set (for single planes the
- * plane layout, row-major or tiled where the plane is padded and 2048 <= 2nx <= 8192, and
- * the row-pass form of the row-major plane; for nz > 1 the row-pass form and the z-stack
- * chunk size) on the given buffers, times each on the stream with HIP events (the call
+ * plane layout, row-major or tiled where the plane is padded and 2048 <= 2nx <= 8192, the
+ * row-pass form of the row-major plane and the column form of the tiled plane; for nz > 1
+ * the row-pass form and the z-stack chunk size) on the given buffers, times each on the stream with HIP events (the call
  * synchronises the stream), and keeps the fastest in the context for (kind, nx, ny,
  * precision, flags, nz); later cwo_asm / cwo_fresnel calls (nz = 1) and z-stacks of nz
  * planes with those parameters use it. Results do not depend on the schedule. in:
@@ -271,8 +276,9 @@ cwo_status cwo_autotune(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const voi
 /* Install a schedule for (kind, nx, ny, precision, flags, nz) without timing anything (one
  * chosen elsewhere, e.g. read from a tune cache); a null t removes the context's schedule
  * so the defaults apply again. CWO_ERR_INVALID for out-of-range fields (row_form 0..2,
- * zchunk 0..64, layout 0..2), CWO_ERR_UNSUPPORTED for a tiled layout the geometry cannot
- * take. Host only; results never depend on the schedule. */
+ * zchunk 0..64, layout 0..2, col_form 0..2), CWO_ERR_UNSUPPORTED for a tiled layout the
+ * geometry cannot take or a column form other than 0 where the plane is not tiled with
+ * padded columns of 4096 or 8192. Host only; results never depend on the schedule. */
 cwo_status cwo_set_tuning(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const cwo_tuning* t);
 
 /* z-stack: one field propagated to nz distances, the paper's 3-D field built by stacking
@@ -307,7 +313,8 @@ cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip
  * FP16 form also scales each field entering a forward transform by 2^-e, e the binary
  * exponent of its largest component: u, then a2 and a1); arithmetic, u and E_k stay
  * FP32 (E_k's sums FP64). Low precision needs the padded form (no CWO_FLAG_NOPAD).
- * Scratch: ny * 2nx stored values, plus iterations * ny doubles for E_k. */
+ * Scratch: ny * Mx stored values (Mx = 2nx, or nx with CWO_FLAG_NOPAD), plus
+ * iterations * ny * max(1, Mx/1024) doubles for E_k (the rows' error partials). */
 cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* hip_stream);
 

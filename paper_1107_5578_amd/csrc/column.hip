@@ -5,10 +5,14 @@
 
 namespace cwo {
 
-template <class HF, class ST>
+// On the tiled plane a padded column of 8192 runs by default as two transforms of 4096 (one
+// column per block), shorter ones as one transform per column (two columns per thread).
+// ALT launchers (single planes, where the autotuner may pick the column form) also build the
+// other form at 4096 and 8192: col_form 1 full length, 2 split.
+template <class HF, class ST, bool ALT = false>
 static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, size_t plane,
                                const HF& hf, float hscale, const float2* tw, hipStream_t s,
-                               int layout = 0) {
+                               int layout = 0, int col_form = 0) {
     const bool half = (my == 2 * ny);
     using SE = typename ST::E;
     if (layout == 1 && (!half || mx % kTileW != 0)) return hipErrorInvalidValue;
@@ -16,15 +20,23 @@ static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, siz
         using C = ColCfg<MM>;
         const int items = (mx + C::COLS - 1) / C::COLS * batch;
         if (half && layout == 1) {
-            if constexpr (MM == 8192) {
-                // padded columns of length 8192 as two transforms of 4096, one per block
-                hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx * batch),
-                                   dim3(MM / 32), 0, s, (SE*)buf, ny, mx, batch, plane, hf, hscale,
-                                   tw, LayTile{ny});
+            constexpr bool CAN_SPLIT = MM == 8192 || (ALT && MM == 4096);
+            constexpr bool CAN_FULL = MM != 8192 || ALT;
+            const bool split = MM == 8192 ? col_form != 1 : col_form == 2;
+            if (split) {
+                if constexpr (CAN_SPLIT)
+                    hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx * batch),
+                                       dim3(MM / 32), 0, s, (SE*)buf, ny, mx, batch, plane, hf,
+                                       hscale, tw, LayTile{ny});
+                else
+                    return hipErrorInvalidValue;
             } else {
-                hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items), dim3(C::THREADS),
-                                   0, s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw,
-                                   LayTile{ny});
+                if constexpr (CAN_FULL)
+                    hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items),
+                                       dim3(C::THREADS), 0, s, (SE*)buf, ny, mx, batch, plane, hf,
+                                       hscale, tw, LayTile{ny});
+                else
+                    return hipErrorInvalidValue;
             }
         } else if (half) {
             hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS), 0,
@@ -44,9 +56,9 @@ static hipError_t launch_col_impl(void* buf, int ny, int my, int mx, int batch, 
                                   const HF& hf, const Storage& st, const float2* tw,
                                   hipStream_t s) {
     switch (st.prec) {
-        case 0: return launch_col_t<HF, StF32>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout);
-        case 1: return launch_col_t<HF, StF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout);
-        case 2: return launch_col_t<HF, StBF16>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout);
+        case 0: return launch_col_t<HF, StF32, true>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout, st.col_form);
+        case 1: return launch_col_t<HF, StF16, true>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout, st.col_form);
+        case 2: return launch_col_t<HF, StBF16, true>(buf, ny, my, mx, batch, plane, hf, st.col_scale, tw, s, st.layout, st.col_form);
     }
     return hipErrorInvalidValue;
 }

@@ -436,7 +436,7 @@ TuneKey tune_key(const cwo_params* p, int kind, int nz) {
 cwo_tuning tuned_for(cwo_ctx* c, const cwo_params* p, int kind, int nz) {
     std::lock_guard<std::mutex> g(c->tmu);
     auto it = c->tuned.find(tune_key(p, kind, nz));
-    return it == c->tuned.end() ? cwo_tuning{0, 0, 0.0f, 0} : it->second;
+    return it == c->tuned.end() ? cwo_tuning{0, 0, 0.0f, 0, 0} : it->second;
 }
 
 // Whether the tiled plane can be used for this geometry at all (padded planes of
@@ -453,6 +453,12 @@ int plane_layout(const Geometry& g, const cwo_tuning& t) {
     return cwo::tiled_ok(g.nx, g.ny, g.mx, g.my) ? 1 : 0;
 }
 
+// Column forms of a plane laid out as `layout` (1 tiled): both forms for padded columns of
+// 4096 or 8192 on the tiled plane, else only the default.
+bool col_forms_possible(const Geometry& g, int layout) {
+    return layout == 1 && g.my == 2 * g.ny && (g.my == 4096 || g.my == 8192);
+}
+
 void set_tuned(cwo_ctx* c, const TuneKey& k, const cwo_tuning* t) {
     std::lock_guard<std::mutex> g(c->tmu);
     if (t) c->tuned[k] = *t;
@@ -465,7 +471,7 @@ void set_tuned(cwo_ctx* c, const TuneKey& k, const cwo_tuning* t) {
 // successful cwo_autotune rewrites the file with all schedules the context knows: a JSON
 // array of flat objects, one per line, e.g.
 //   {"kind": 1, "nx": 2048, "ny": 2048, "precision": 0, "flags": 0, "nz": 1,
-//    "row_form": 1, "zchunk": 0, "layout": 2, "us_per_plane": 126.5}
+//    "row_form": 1, "zchunk": 0, "layout": 2, "us_per_plane": 126.5, "col_form": 1}
 // (written on one line). Lines that do not parse are ignored; a missing file is no error.
 const char* tune_cache_path() {
     const char* p = std::getenv("CWO_TUNE_CACHE");
@@ -484,10 +490,11 @@ void load_tune_cache(cwo_ctx* c) {
         const int n = std::sscanf(line,
                                   " {\"kind\": %d, \"nx\": %d, \"ny\": %d, \"precision\": %d, "
                                   "\"flags\": %d, \"nz\": %d, \"row_form\": %d, \"zchunk\": %d, "
-                                  "\"layout\": %d, \"us_per_plane\": %f",
+                                  "\"layout\": %d, \"us_per_plane\": %f, \"col_form\": %d",
                                   &k.kind, &k.nx, &k.ny, &k.precision, &k.flags, &k.nz, &t.row_form,
-                                  &t.zchunk, &t.layout, &t.us_per_plane);
-        if (n == 10) set_tuned(c, k, &t);
+                                  &t.zchunk, &t.layout, &t.us_per_plane, &t.col_form);
+        // (records written before the column form existed end after us_per_plane)
+        if (n >= 10) set_tuned(c, k, &t);
     }
     std::fclose(f);
 }
@@ -507,9 +514,9 @@ void save_tune_cache(cwo_ctx* c) {
         std::fprintf(f,
                      " {\"kind\": %d, \"nx\": %d, \"ny\": %d, \"precision\": %d, \"flags\": %d, "
                      "\"nz\": %d, \"row_form\": %d, \"zchunk\": %d, \"layout\": %d, "
-                     "\"us_per_plane\": %.3f}%s\n",
+                     "\"us_per_plane\": %.3f, \"col_form\": %d}%s\n",
                      k.kind, k.nx, k.ny, k.precision, k.flags, k.nz, t.row_form, t.zchunk, t.layout,
-                     (double)t.us_per_plane, ++i < c->tuned.size() ? "," : "");
+                     (double)t.us_per_plane, t.col_form, ++i < c->tuned.size() ? "," : "");
     }
     std::fprintf(f, "]\n");
     const bool ok = std::fclose(f) == 0;
@@ -548,6 +555,9 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
     const cwo_tuning tune = tuned_for(c, p, kind, 1);
     sto.row_form = tune.row_form;
     sto.layout = plane_layout(g, tune);
+    sto.col_form = col_forms_possible(g, sto.layout) && tune.col_form >= 0 && tune.col_form <= 2
+                       ? tune.col_form
+                       : 0;
     if (p->precision != CWO_PREC_F32) {
         // FP16/BF16 storage: 2^-floor(log2(Mx)/2) before the row transform, 1/My in the
         // column pass, the rest of 1/Mx at the end (all powers of two); FP16 also scales
@@ -1689,15 +1699,28 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
                        : zstack_locked(c, c->ws, p, kind, zs.data(), nz, in, outs.data(), s);
     };
     hipEvent_t a = take_event(c), b = take_event(c);
-    cwo_tuning found{0, 0, 0.0f, 0};
+    cwo_tuning found{0, 0, 0.0f, 0, 0};
     float best_ms = -1.0f;
-    std::vector<std::pair<int, int>> cands;
-    for (int lay : layouts)
-        for (int f : (lay == 2 ? std::vector<int>{0} : forms)) cands.push_back({lay, f});
-    for (const auto& lf : cands) {
-        const int f = lf.second;
+    // (layout, row form, column form): the tiled plane has one row form and, for padded
+    // columns of 4096 or 8192, two column forms
+    struct Cand {
+        int layout, row_form, col_form;
+    };
+    std::vector<Cand> cands;
+    for (int lay : layouts) {
+        if (lay == 2) {
+            if (col_forms_possible(g, 1))
+                for (int cf : {1, 2}) cands.push_back({lay, 0, cf});
+            else
+                cands.push_back({lay, 0, 0});
+        } else {
+            for (int f : forms) cands.push_back({lay, f, 0});
+        }
+    }
+    for (const Cand& cd : cands) {
+        const int f = cd.row_form;
         for (int zc : chunks) {
-            const cwo_tuning cand{f, zc, 0.0f, lf.first};
+            const cwo_tuning cand{f, zc, 0.0f, cd.layout, cd.col_form};
             set_tuned(c, key, &cand);
             st = run();  // warm-up: allocations and tables
             if (st != CWO_OK) break;
@@ -1714,7 +1737,7 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
             ms /= kReps;
             if (best_ms < 0.0f || ms < best_ms) {
                 best_ms = ms;
-                found = cwo_tuning{f, zc, (float)(1000.0 * ms / nz), lf.first};
+                found = cwo_tuning{f, zc, (float)(1000.0 * ms / nz), cd.layout, cd.col_form};
             }
         }
         if (st != CWO_OK) break;
@@ -1742,9 +1765,13 @@ cwo_status cwo_set_tuning(cwo_ctx* c, const cwo_params* p, int32_t nz, const cwo
         return CWO_OK;
     }
     if (t->row_form < 0 || t->row_form > 2 || t->zchunk < 0 || t->zchunk > cwo::kZChunk ||
-        t->layout < 0 || t->layout > 2 || !(t->us_per_plane >= 0.0f))
+        t->layout < 0 || t->layout > 2 || t->col_form < 0 || t->col_form > 2 ||
+        !(t->us_per_plane >= 0.0f))
         return CWO_ERR_INVALID;
-    if (t->layout == 2 && !(nz == 1 && tiles_possible(geometry(p)))) return CWO_ERR_UNSUPPORTED;
+    const Geometry g = geometry(p);
+    if (t->layout == 2 && !(nz == 1 && tiles_possible(g))) return CWO_ERR_UNSUPPORTED;
+    if (t->col_form != 0 && !(nz == 1 && col_forms_possible(g, plane_layout(g, *t))))
+        return CWO_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(c->mu);
     set_tuned(c, key, t);
     return CWO_OK;
@@ -1792,8 +1819,9 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     void* spec = ensure(c, c->ws, c->ws.scratch, elem_bytes(p->precision) * (size_t)g.ny * g.mx, &st);
     if (!spec) return st;
     double* num = nullptr;
+    const size_t nrow = (size_t)g.ny * cwo::gs_partials(g.mx);  // error partials per iteration
     if (errors) {
-        num = (double*)ensure(c, c->ws, c->ws.gsnum, sizeof(double) * ((size_t)iterations * g.ny + 1),
+        num = (double*)ensure(c, c->ws, c->ws.gsnum, sizeof(double) * ((size_t)iterations * nrow + 1),
                               &st);
         if (!num) return st;
     }
@@ -1838,7 +1866,7 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
                     return cwo::launch_col_asm(spec, g.ny, g.my, g.mx, 1, 0, fwd, sto, twy, s);
                 }));
-        double* nk = num ? num + (size_t)k * g.ny : nullptr;
+        double* nk = num ? num + (size_t)k * nrow : nullptr;
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_GS, s, [&] {
                     return cwo::launch_row_gs(spec, a2, nullptr, nk, g.nx, g.ny, g.mx, g2, twx, s);
                 }));
@@ -1852,8 +1880,8 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
         if (g1.dyn_fwd) g2.dyn_inv = g1.dyn_fwd + 1;
     }
     if (errors) {
-        double* den = num + (size_t)iterations * g.ny;
-        CWO_HIP(c, cwo::launch_gs_errors(num, a2, den, errors, g.nx, g.ny, iterations, s));
+        double* den = num + (size_t)iterations * nrow;
+        CWO_HIP(c, cwo::launch_gs_errors(num, a2, den, errors, g.nx, g.ny, g.mx, iterations, s));
     }
     return CWO_OK;
 }

@@ -14,31 +14,25 @@ namespace cwo {
 // and the constrained field by fwd_scale * (*dyn_fwd) before the forward transform (null
 // dyn pointers count as 1), so FP16 storage stays in range.
 
-// Sum of one double per thread over the T threads of a row (T a power of two; the row's
-// threads are T consecutive lanes, or whole wavefronts when T >= 64): a butterfly of
-// cross-lane exchanges within the wavefront, then the wavefront partials added in wavefront
-// order by the row's first thread. The order is fixed, so the sum is deterministic. red:
-// T/64 doubles of LDS for the row. All threads of the block call it (block barriers).
+// Error partials of one row: each thread's double summed over its wavefront's share of the
+// row (the row's T threads are T consecutive lanes, or whole wavefronts when T >= 64) by a
+// butterfly of cross-lane exchanges in a fixed order, and stored by the share's first lane
+// at num[row * P + w], w the row's wavefront (P = max(1, T/64) partials per row). The
+// iteration's error sums them later in a fixed order too, so it stays deterministic; no
+// block barrier is taken here.
+// All lanes of the wavefront call it (store: whether this row exists).
 template <int T>
-__device__ __forceinline__ double row_sum(double x, double* red, int j) {
+__device__ __forceinline__ void row_partials(double x, double* __restrict__ num, int row, int j,
+                                             bool store) {
     constexpr int W = T < 64 ? T : 64;
+    constexpr int P = T < 64 ? 1 : T / 64;
 #pragma unroll
     for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if constexpr (T <= 64) {
-        return x;
-    } else {
-        lds_barrier();
-        if ((j & 63) == 0) red[j >> 6] = x;
-        lds_barrier();
-        double t = 0.0;
-        if (j == 0) {
-#pragma unroll
-            for (int i = 0; i < T / 64; ++i) t += red[i];
-        }
-        lds_barrier();
-        return t;
-    }
+    if (store && (j & (W - 1)) == 0) num[(size_t)row * P + j / W] = x;
 }
+
+// Error partials per row for rows of m points (the row kernels run m/16 threads per row).
+constexpr int gs_partials_per_row(int m) { return m / 16 < 64 ? 1 : m / 16 / 64; }
 
 template <int M, bool HALF, class ST>
 __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
@@ -89,10 +83,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
             v[0][r] = make_float2(0.f, 0.f);  // the padding of the next forward transform
         }
     }
-    if (num) {
-        const double t = row_sum<T>(acc, reinterpret_cast<double*>(my_lds), j);
-        if (j == 0 && valid) num[row] = t;
-    }
+    if (num) row_partials<T>(acc, num, row, j, valid);
     if (out) {
         if (valid) {
             float2* orow = out + (size_t)row * nx;
@@ -124,14 +115,35 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_row_gs(
 // constraint and the row's error partial; then either the constrained field to out, or
 // the re-padded forward transform regrouped by tile and stored back in place (each block
 // reads and writes only its own groups' tile rows).
-template <int M, class ST>
-__global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
+// RPB rows per block
+template <int M, int RPB_>
+struct GsTileCfg {
+    static constexpr int E = 16;
+    static constexpr int T = M / E;
+    static constexpr int RPB = RPB_;
+    static constexpr int THREADS = T * RPB;
+    static constexpr int TS = kTileW * RPB;
+    static constexpr int XCH = RPB * lds_elems<M>();
+    static constexpr int TRN = (M / kTileW) * TS;
+    static constexpr int LDS = XCH > TRN ? XCH : TRN;
+};
+template <int M, int RPB, class SE>
+struct GsTileChunks {
+    using C = GsTileCfg<M, RPB>;
+    static constexpr int CE = 16 / (int)sizeof(SE);
+    static constexpr int PER_TILE = RPB * kTileW / CE;
+    static constexpr int CPT = (M / kTileW) * PER_TILE / C::THREADS;
+    static_assert(CPT * C::THREADS == (M / kTileW) * PER_TILE, "chunks");
+};
+
+template <int M, class ST, int RPB>
+__global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) void k_row_gs_tile(
     typename ST::E* __restrict__ spec, const float* __restrict__ amp, float2* __restrict__ out,
     double* __restrict__ num, int nx, int ny, float scale, const float* __restrict__ dyn_inv,
     float fwd_scale, const float* __restrict__ dyn_fwd, const float2* __restrict__ tw) {
-    using C = TileRowCfg<M>;
+    using C = GsTileCfg<M, RPB>;
     using SE = typename ST::E;
-    using K = TileChunks<M, SE>;
+    using K = GsTileChunks<M, RPB, SE>;
     using PK = Pack<SE, K::CE>;
     constexpr int E = C::E, T = C::T, NL = E / 2;
     __shared__ float2 lds[C::LDS];
@@ -215,10 +227,7 @@ __global__ __launch_bounds__(TileRowCfg<M>::THREADS) void k_row_gs_tile(
             }
         }
         if (more) load_amp(g + ir.step, acur, jt);
-        if (num) {
-            const double t = row_sum<T>(acc, reinterpret_cast<double*>(my_lds), jt);
-            if (jt == 0) num[row] = t;
-        }
+        if (num) row_partials<T>(acc, num, row, jt, true);
         if (out) {
             float2* orow = out + (size_t)row * nx;
 #pragma unroll
@@ -271,13 +280,14 @@ __global__ __launch_bounds__(256) void k_gs_den(const float* __restrict__ amp, d
     if (threadIdx.x == 0) *den = red[0];
 }
 
+// iteration k's error from its n = ny * P row partials, summed in a fixed order
 __global__ __launch_bounds__(256) void k_gs_errors(const double* __restrict__ num,
                                                    const double* __restrict__ den,
-                                                   float* __restrict__ errors, int ny) {
+                                                   float* __restrict__ errors, int n) {
     __shared__ double red[256];
     const int k = blockIdx.x;
     double t = 0.0;
-    for (int i = threadIdx.x; i < ny; i += 256) t += num[(size_t)k * ny + i];
+    for (int i = threadIdx.x; i < n; i += 256) t += num[(size_t)k * n + i];
     red[threadIdx.x] = t;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
@@ -301,8 +311,12 @@ hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int 
         CWO_DISPATCH_M(mx, {
             // (rows of 8192 stay row-major in this loop: no split form of the fused kernel)
             if constexpr (MM >= 2048 && MM <= 4096) {
-                using C = TileRowCfg<MM>;
-                auto k = k_row_gs_tile<MM, ST>;
+                // rows of 4096: one row per block, two blocks per CU (6 % faster than two
+                // rows per block, measured at 2048^2); rows of 2048: two rows per block
+                constexpr int RPB = MM == 4096 ? 1 : 2;
+                using C = GsTileCfg<MM, RPB>;
+                if (ny % C::RPB != 0) return hipErrorInvalidValue;
+                auto k = k_row_gs_tile<MM, ST, RPB>;
                 hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),
                                    dim3(C::THREADS), 0, s, (SE*)spec, amp, out, num, nx, ny,
                                    scale, dyn_inv, fwd_scale, dyn_fwd, tw);
@@ -342,11 +356,13 @@ hipError_t launch_row_gs(void* spec, const float* amp, float2* out, double* num,
     return hipErrorInvalidValue;
 }
 
+int gs_partials(int mx) { return gs_partials_per_row(mx); }
+
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
-                            int nx, int ny, int iters, hipStream_t s) {
+                            int nx, int ny, int mx, int iters, hipStream_t s) {
     hipLaunchKernelGGL(k_gs_den, dim3(1), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
     hipLaunchKernelGGL(k_gs_errors, dim3(iters), dim3(256), 0, s, num, (const double*)den_work,
-                       errors, ny);
+                       errors, ny * gs_partials_per_row(mx));
     return hipGetLastError();
 }
 

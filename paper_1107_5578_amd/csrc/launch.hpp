@@ -49,6 +49,8 @@ struct Storage {
     const float* dyn_inv = nullptr;
     int row_form = 0;  // row passes: 0 default, 1 persistent with prefetch, 2 one group per block
     int layout = 0;    // padded plane between the passes: 0 row-major, 1 tiled (see tiled_ok)
+    int col_form = 0;  // tiled plane, padded columns of 4096 / 8192: 0 default, 1 two columns
+                       // per thread at full length, 2 two half-length transforms per column
 };
 
 // The tiled plane layout is taken for padded planes (Mx = 2Nx, My = 2Ny) with
@@ -149,13 +151,16 @@ struct GsScale {
 // storage of gsc.prec, the output of a column pass): inverse row FFT, keep the first nx
 // values scaled as gsc says, replace each value u by a*u/|u| (a where u == 0) with a from
 // amp ([ny][nx] float32), and, if num is not null, store the row's FP64 sum of
-// (|u| - a)^2 in num[row]. Then either (out == nullptr) zero-pad and forward row FFT back
-// into spec, or write the constrained field to out ([ny][nx] complex64).
+// (|u| - a)^2 as P = gs_partials(mx) partials at num[row*P .. row*P + P-1]. Then either
+// (out == nullptr) zero-pad and forward row FFT back into spec, or write the constrained
+// field to out ([ny][nx] complex64).
 hipError_t launch_row_gs(void* spec, const float* amp, float2* out, double* num, int nx, int ny,
                          int mx, const GsScale& gsc, const float2* tw, hipStream_t s);
-// errors[k] = sqrt(sum_rows num[k*ny + row] / sum(amp^2)), k < iters; den_work holds 1 double.
+int gs_partials(int mx);
+// errors[k] = sqrt(sum of num[k*ny*P ..] over the ny*P partials / sum(amp^2)), k < iters,
+// P = gs_partials(mx); den_work holds 1 double.
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
-                            int nx, int ny, int iters, hipStream_t s);
+                            int nx, int ny, int mx, int iters, hipStream_t s);
 
 // Fresnel transfer-function factors of up to kZChunk planes that share the geometry:
 // plane k gets Hx_k = C_k * DFT_mx(hx_k) at out + k*(mx+my) and Hy_k = DFT_my(hy_k) right

@@ -109,7 +109,8 @@ class SFresnel(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """cwo_tuning: the schedule picked by cwo_autotune."""
     _fields_ = [("row_form", ctypes.c_int32), ("zchunk", ctypes.c_int32),
-                ("us_per_plane", ctypes.c_float), ("layout", ctypes.c_int32)]
+                ("us_per_plane", ctypes.c_float), ("layout", ctypes.c_int32),
+                ("col_form", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -484,7 +485,7 @@ class Context:
     def autotune(self, u, nz=1, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, kind="asm",
                  precision="f32", nopad=False, stream=None):
         """Pick and keep the fastest schedule for this parameter set (cwo_autotune);
-        returns (row_form, zchunk, us_per_plane, layout)."""
+        returns (row_form, zchunk, us_per_plane, layout, col_form)."""
         import torch
         u = self._field(u)
         ny, nx = u.shape
@@ -497,14 +498,14 @@ class Context:
                                     self._stream(u, stream), ctypes.byref(t))
         if st != CWO_OK:
             raise CwoError(st, "cwo_autotune")
-        return t.row_form, t.zchunk, t.us_per_plane, t.layout
+        return t.row_form, t.zchunk, t.us_per_plane, t.layout, t.col_form
 
     def set_tuning(self, nx, ny, nz=1, kind="asm", precision="f32", nopad=False, row_form=0,
-                   zchunk=0, layout=0, clear=False):
+                   zchunk=0, layout=0, clear=False, col_form=0):
         """Install a schedule for this parameter set (cwo_set_tuning), or remove it."""
         k = KINDS[kind] if isinstance(kind, str) else int(kind)
         p = make_params(nx, ny, 10e-6, None, 633e-9, 0.1, k, precision, nopad)
-        t = Tuning(int(row_form), int(zchunk), 0.0, int(layout))
+        t = Tuning(int(row_form), int(zchunk), 0.0, int(layout), int(col_form))
         st = self._lib.cwo_set_tuning(self.handle, ctypes.byref(p), int(nz),
                                       None if clear else ctypes.byref(t))
         if st != CWO_OK:
