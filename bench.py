@@ -105,18 +105,18 @@ def cpu_baseline(u_np, cfg, kind="asm", min_seconds: float = 10.0, max_planes: i
                                    "sample": "%d whole plane(s), 1 thread (%.1f s)" % (done1, dt1)}}
 
 
-def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm):
+def time_zstack(ctx, torch, u, zs, pitch, lam, reps, warm, precision="f32"):
     """Planes/s of one z-stack call (all planes) over `reps` calls, HIP events."""
     out = torch.empty((len(zs),) + tuple(u.shape), dtype=torch.complex64, device=u.device)
     for _ in range(warm):
-        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out)
+        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out, precision=precision)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(u.device)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(reps):
-        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out)
+        ctx.zstack(u, zs, pitch, pitch, lam, kind="asm", out=out, precision=precision)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
@@ -461,6 +461,21 @@ def main():
         batched["zstack_1024x64"] = {"planes_per_s": round(c3_pps, 1), "ms_per_stack": round(c3_ms, 4),
                                      "schedule": {"row_form": form, "zchunk": zchunk},
                                      "workload": "1024x1024 speckle, 4um, 633nm, 64 z in [0.05, 0.2] m"}
+        # the same stack with FP16 / BF16 storage of the spectrum and the planes (autotuned
+        # for that precision), each plane's error against the complex64 stack
+        ref3 = ctx.zstack(u3, z3, c3.pitch, c3.pitch, c3.wavelength, kind="asm")
+        for prec in ("f16", "bf16"):
+            pf, pz, _, _, _ = ctx.autotune(u3, 64, c3.pitch, c3.pitch, c3.wavelength, 0.1,
+                                           precision=prec)
+            p_pps, p_ms = time_zstack(ctx, torch, u3, z3, c3.pitch, c3.wavelength, 10, 2, prec)
+            y3 = ctx.zstack(u3, z3, c3.pitch, c3.pitch, c3.wavelength, kind="asm", precision=prec)
+            err = float((torch.linalg.vector_norm(y3 - ref3) /
+                         torch.linalg.vector_norm(ref3)).item())
+            batched["zstack_1024x64"][prec + "_storage"] = {
+                "planes_per_s": round(p_pps, 1), "ms_per_stack": round(p_ms, 4),
+                "schedule": {"row_form": pf, "zchunk": pz}, "rel_l2_vs_complex64": float("%.3e" % err)}
+            del y3
+        del ref3
         del u3
         # 64 independent fields, each at its own distance (and every third one Fresnel): one
         # cwo_batch (one launch per pass, a transfer function per plane) vs the same 64

@@ -288,7 +288,10 @@ cwo_status cwo_set_tuning(cwo_ctx* ctx, const cwo_params* p, int32_t nz, const c
  * device. The row transform of the field and the forward column transforms are done once;
  * planes are processed in chunks of at most 64 that fit the context's budget
  * (CWO_ERR_NOMEM if not even one plane fits). Plane k equals cwo_asm / cwo_fresnel with
- * z = z[k] up to rounding order. */
+ * z = z[k] up to rounding order. p->precision picks the storage of the shared spectrum and
+ * of the chunk's planes (complex64, or FP16 / BF16 pairs with the power-of-two scalings of
+ * cwo_asm: half the scratch per plane; the padded form only); arithmetic and out stay
+ * FP32. */
 cwo_status cwo_zstack(cwo_ctx* ctx, const cwo_params* p, const double* z, int32_t nz,
                       const void* in, void* out, void* hip_stream);
 

@@ -632,22 +632,23 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
     if (!twy) return st;
     const size_t plane = (size_t)g.ny * g.mx;
     const size_t len = (size_t)(g.mx + g.my);
+    const size_t eb = elem_bytes(p->precision);  // bytes per stored complex value
     // chunk size: the shared spectrum and all planes of a chunk within the budget
     int zc = std::min(nz, cwo::kZChunk);
     const cwo_tuning tune = tuned_for(c, p, kind, nz);
     if (tune.zchunk > 0) zc = std::min(zc, tune.zchunk);
     if (ws.budget) {
         const size_t fres = kind == CWO_FRESNEL_CONV ? sizeof(float2) * len : 0;
-        const size_t per_plane = sizeof(float2) * plane + fres;
-        const size_t base = sizeof(float2) * plane + (kind == CWO_FRESNEL_CONV ? sizeof(double2) * len : 0);
+        const size_t per_plane = eb * plane + fres;
+        const size_t base = eb * plane + (kind == CWO_FRESNEL_CONV ? sizeof(double2) * len : 0);
         if (ws.budget < base + per_plane) return CWO_ERR_NOMEM;
         const size_t fit = (ws.budget - base) / per_plane;
         zc = (int)std::min<size_t>((size_t)zc, fit);
     }
-    float2* buf = (float2*)ensure(c, ws, ws.scratch, sizeof(float2) * plane * (size_t)(1 + zc), &st);
+    char* buf = (char*)ensure(c, ws, ws.scratch, eb * plane * (size_t)(1 + zc), &st);
     if (!buf) return st;
-    float2* spec = buf;
-    float2* zbuf = buf + plane;
+    void* spec = buf;
+    void* zbuf = buf + eb * plane;
     float2* tabs = nullptr;
     double2* work = nullptr;
     if (kind == CWO_FRESNEL_CONV) {
@@ -656,11 +657,29 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
         work = (double2*)ensure(c, ws, ws.fwork, sizeof(double2) * len, &st);
         if (!work) return st;
     }
+    // storage of the shared spectrum and the planes: complex64 with 1/(Mx My) at the end,
+    // or 16-bit pairs with the power-of-two scalings of a single propagation
+    cwo::Storage sto;
+    sto.out_scale = 1.0f / ((float)g.mx * (float)g.my);
+    sto.row_form = tune.row_form;
+    if (p->precision != CWO_PREC_F32) {
+        sto.prec = p->precision == CWO_PREC_F16_STORAGE ? 1 : 2;
+        const int kx = ilog2(g.mx) / 2;
+        sto.in_scale = std::ldexp(1.0f, -kx);
+        sto.col_scale = 1.0f / (float)g.my;
+        sto.out_scale = std::ldexp(1.0f, kx) / (float)g.mx;
+        if (sto.prec == 1) {
+            float* rw = (float*)ensure(c, ws, ws.rwork, sizeof(float) * (2 + cwo::kRangeBlocks), &st);
+            if (!rw) return st;
+            CWO_HIP(c, cwo::launch_range_scale((const float2*)in, (size_t)g.ny * g.nx, rw, s));
+            sto.dyn_scale = rw;
+            sto.dyn_inv = rw + 1;
+        }
+    }
     CWO_HIP(c, timed(c, CWO_STAGE_ROW_FWD, s, [&] {
-                return cwo::launch_row_fwd((const float2*)in, spec, g.nx, g.ny, g.mx, 1, 0, 0, twx, s,
-                                           tune.row_form);
+                return cwo::launch_row_fwd((const float2*)in, spec, g.nx, g.ny, g.mx, 1, 0, 0, sto,
+                                           twx, s);
             }));
-    const float scale = 1.0f / ((float)g.mx * (float)g.my);
     for (int k0 = 0; k0 < nz; k0 += zc) {
         const int n = std::min(zc, nz - k0);
         cwo::ZChunk ch;
@@ -673,7 +692,8 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
         if (kind == CWO_ANGULAR) {
             const cwo::AsmScalars a = asm_scalars(p, g, 0.0);
             CWO_HIP(c, timed(c, CWO_STAGE_COL_Z, s, [&] {
-                        return cwo::launch_col_z_asm(spec, zbuf, g.ny, g.my, g.mx, plane, a, ch, twy, s);
+                        return cwo::launch_col_z_asm(spec, zbuf, g.ny, g.my, g.mx, plane, a, ch, sto,
+                                                     twy, s);
                     }));
         } else {
             const cwo::FresnelPlanes fp = fresnel_planes(p, g, z + k0, n);
@@ -681,11 +701,11 @@ cwo_status zstack_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int kin
                              [&] { return cwo::launch_fresnel_planes(work, tabs, fp, s); }));
             CWO_HIP(c, timed(c, CWO_STAGE_COL_Z, s, [&] {
                         return cwo::launch_col_z_fresnel(spec, zbuf, g.ny, g.my, g.mx, plane, tabs, n,
-                                                         twy, s);
+                                                         sto, twy, s);
                     }));
         }
         CWO_HIP(c, timed(c, CWO_STAGE_ROW_INV, s, [&] {
-                    return cwo::launch_row_inv_z(zbuf, ch, g.nx, g.ny, g.mx, plane, scale, twx, s);
+                    return cwo::launch_row_inv_z(zbuf, ch, g.nx, g.ny, g.mx, plane, sto, twx, s);
                 }));
     }
     return CWO_OK;
@@ -1670,7 +1690,7 @@ cwo_status cwo_autotune(cwo_ctx* c, const cwo_params* p, int32_t nz, const void*
                         void* stream, cwo_tuning* best) {
     if (!c || !p || !in || !out || nz < 1) return CWO_ERR_INVALID;
     const int kind = p->kind;
-    cwo_status st = validate(p, kind, nz == 1);
+    cwo_status st = validate(p, kind, true);  // 16-bit storage: single planes and z-stacks
     if (st != CWO_OK) return st;
     std::lock_guard<std::mutex> lock(c->mu);
     st = begin(c);
@@ -1781,7 +1801,7 @@ cwo_status cwo_zstack(cwo_ctx* c, const cwo_params* p, const double* z, int32_t 
                       void* out, void* stream) {
     if (!c || !p || !z || !in || !out || nz < 1) return CWO_ERR_INVALID;
     const int kind = p->kind;
-    cwo_status st = validate_geometry(p, kind);
+    cwo_status st = validate_geometry(p, kind, true);  // 16-bit storage: padded planes
     if (st != CWO_OK) return st;
     for (int k = 0; k < nz; ++k)
         if ((st = validate_z(z[k], kind)) != CWO_OK) return st;

@@ -124,16 +124,19 @@ hipError_t launch_row_inv(const float2* in, float2* out, int nx, int ny, int mx,
 // z-stack column pass: spec holds the row spectra [ny][mx] of one field (read only);
 // for each plane k < zc.nz the column spectrum is multiplied by H(z_k), inverse
 // transformed and written to zbuf + k * zplane ([ny][mx] each).
-hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                            size_t zplane, const AsmScalars& a, const ZChunk& zc,
+// spec and zbuf hold values in the storage st.prec (padded planes only for 16-bit); the
+// stored planes are multiplied by st.col_scale.
+hipError_t launch_col_z_asm(const void* spec, void* zbuf, int ny, int my, int mx, size_t zplane,
+                            const AsmScalars& a, const ZChunk& zc, const Storage& st,
                             const float2* tw, hipStream_t s);
 // Fresnel: the 1-D factors of plane k are at h + k * (mx + my) (Hx with C, then Hy).
-hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                                size_t zplane, const float2* h, int nz, const float2* tw,
-                                hipStream_t s);
-// Row inverse of zc.nz planes of zbuf into the per-plane outputs zc.out[k].
-hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
-                            size_t zplane, float scale, const float2* tw, hipStream_t s);
+hipError_t launch_col_z_fresnel(const void* spec, void* zbuf, int ny, int my, int mx,
+                                size_t zplane, const float2* h, int nz, const Storage& st,
+                                const float2* tw, hipStream_t s);
+// Row inverse of zc.nz planes of zbuf (storage st.prec) into the per-plane outputs
+// zc.out[k], multiplied by st.out_scale * (*st.dyn_inv).
+hipError_t launch_row_inv_z(const void* zbuf, const ZChunk& zc, int nx, int ny, int mx,
+                            size_t zplane, const Storage& st, const float2* tw, hipStream_t s);
 
 // Scalings of the ping-pong row kernel for spectra stored as Storage::prec (0 complex64,
 // 1 FP16, 2 BF16): the inverse row transform is multiplied by scale * (*dyn_inv), and

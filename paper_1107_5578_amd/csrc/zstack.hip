@@ -78,43 +78,45 @@ struct ZSetFresnel {
     int mx, nz;
 };
 
-template <int M, bool HALF>
-__device__ __forceinline__ void zcol_load(const float2* __restrict__ src, int ny, int mx, int j,
-                                          bool active, float2 (&v)[1][ZColCfg<M>::E]) {
+template <int M, bool HALF, class ST>
+__device__ __forceinline__ void zcol_load(const typename ST::E* __restrict__ src, int ny, int mx,
+                                          int j, bool active, float2 (&v)[1][ZColCfg<M>::E]) {
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
         const bool ld = active && (HALF ? (r < E / 2) : (y < ny));
-        v[0][r] = ld ? src[(size_t)y * mx] : make_float2(0.f, 0.f);
+        v[0][r] = ld ? ST::dec(src[(size_t)y * mx]) : make_float2(0.f, 0.f);
     }
 }
 
 // The z-stack planes are written column-major (element (y, x) of a plane at x*ny + y):
 // each column is contiguous, so a wavefront stores whole cache lines. Lines of these
 // planes are never read before they are written; row-major stores of single columns
-// would leave partially written lines in L2.
-template <int M, bool HALF>
-__device__ __forceinline__ void zcol_store(float2* __restrict__ dst, int ny, int j, bool active,
-                                           const float2 (&w)[1][ZColCfg<M>::E]) {
+// would leave partially written lines in L2. hscale (a power of two; 1 for complex64)
+// multiplies the stored values.
+template <int M, bool HALF, class ST>
+__device__ __forceinline__ void zcol_store(typename ST::E* __restrict__ dst, int ny, int j,
+                                           bool active, const float2 (&w)[1][ZColCfg<M>::E],
+                                           float hscale) {
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int y = j + r * T;
         const bool st = active && (HALF ? (r < E / 2) : (y < ny));
-        if (st) dst[y] = w[0][r];
+        if (st) dst[y] = ST::enc(make_float2(w[0][r].x * hscale, w[0][r].y * hscale));
     }
 }
 
 // The per-bin factor K of the thread's column is parked in LDS (each thread reads back
 // only what it wrote, so no barrier is involved): registers hold the forward spectrum
 // and the twiddles, which would not fit beside K at two waves per SIMD.
-template <int M, bool HALF, class ZH>
+template <int M, bool HALF, class ZH, class ST>
 __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
-    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
-    ZSetAsm<ZH> zs, const float2* __restrict__ tw) {
+    const typename ST::E* __restrict__ spec, typename ST::E* __restrict__ zbuf, int ny, int mx,
+    size_t zplane, ZSetAsm<ZH> zs, float hscale, const float2* __restrict__ tw) {
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
     __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
     TwCache<M, E> twc;
     twc.load(j, tw);
     float2 v[1][E];
-    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
+    zcol_load<M, HALF, ST>(spec + col, ny, mx, j, active, v);
     fft<M, E, 1, FWD>(v, my_lds, j, twc);
 #pragma unroll
     for (int r = 0; r < E; ++r) my_kb[j + r * T] = zs.h.bin(col, j + r * T);
@@ -141,14 +143,15 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_asm(
 #pragma unroll
         for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], zs.h.at(my_kb[j + r * T], zl, c0));
         fft<M, E, 1, INV>(w, my_lds, j, twc);
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
+        zcol_store<M, HALF, ST>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w,
+                                hscale);
     }
 }
 
-template <int M, bool HALF>
+template <int M, bool HALF, class ST>
 __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
-    const float2* __restrict__ spec, float2* __restrict__ zbuf, int ny, int mx, size_t zplane,
-    ZSetFresnel zs, const float2* __restrict__ tw) {
+    const typename ST::E* __restrict__ spec, typename ST::E* __restrict__ zbuf, int ny, int mx,
+    size_t zplane, ZSetFresnel zs, float hscale, const float2* __restrict__ tw) {
     using C = ZColCfg<M>;
     constexpr int E = C::E, T = C::T;
     __shared__ float2 lds[C::PAIRS * C::LDS_PAIR];
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
     TwCache<M, E> twc;
     twc.load(j, tw);
     float2 v[1][E];
-    zcol_load<M, HALF>(spec + col, ny, mx, j, active, v);
+    zcol_load<M, HALF, ST>(spec + col, ny, mx, j, active, v);
     fft<M, E, 1, FWD>(v, my_lds, j, twc);
     for (int k = 0; k < zs.nz; ++k) {
         const float2* hk = zs.h + (size_t)k * zs.stride;
@@ -171,7 +174,8 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
 #pragma unroll
         for (int r = 0; r < E; ++r) w[0][r] = cmul(v[0][r], cmul(hx, hk[zs.mx + j + r * T]));
         fft<M, E, 1, INV>(w, my_lds, j, twc);
-        zcol_store<M, HALF>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w);
+        zcol_store<M, HALF, ST>(zbuf + (size_t)k * zplane + (size_t)col * ny, ny, j, active, w,
+                                hscale);
     }
 }
 
@@ -181,13 +185,15 @@ __global__ __launch_bounds__(ZColCfg<M>::THREADS) void k_col_z_fresnel(
 // rows, reading P contiguous elements (16 bytes) per position; rows are stored to the
 // row-major outputs with the crop and the 1/(Mx*My) scale. Tiles of rows are taken in
 // XCD-contiguous ranges, so the blocks that share an input cache line share an L2.
-template <int M, bool HALF, class OUT>
+template <int M, bool HALF, class OUT, class ST>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per_eu(ColCfg<M>::WAVES_PER_EU))) void k_row_inv_t(
-    const float2* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
-    float scale, const float2* __restrict__ tw) {
+    const typename ST::E* __restrict__ in, OUT outs, int nx, int ny, int batch, size_t in_plane,
+    float scale, const float* __restrict__ dyn_inv, const float2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int E = C::E, T = C::T, P = C::P;
-    using PK = Pack<float2, P>;
+    using SE = typename ST::E;
+    using PK = Pack<SE, P>;
+    if (dyn_inv) scale *= *dyn_inv;
     __shared__ float4 lds4[C::PAIRS * C::LDS_PAIR / 2];
     float2* lds = reinterpret_cast<float2*>(lds4);
     const int tid = threadIdx.x;
@@ -200,13 +206,13 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
         const int pl = it / ntiles, tile = it - pl * ntiles;
         const int y0 = (tile * C::PAIRS + pair) * P;  // first row of this thread (ny is even)
         const bool active = y0 < ny;
-        const float2* base = in + pl * in_plane + (active ? y0 : 0);
+        const SE* base = in + pl * in_plane + (active ? y0 : 0);
         float2 v[P][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const PK t = *reinterpret_cast<const PK*>(base + (size_t)(j + r * T) * ny);
 #pragma unroll
-            for (int p = 0; p < P; ++p) v[p][r] = t.e[p];
+            for (int p = 0; p < P; ++p) v[p][r] = ST::dec(t.e[p]);
         }
         fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
         if (active) {
@@ -232,8 +238,11 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
 
 // ---- host launchers ------------------------------------------------------------
 
-hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny, int mx,
-                            size_t zplane, float scale, const float2* tw, hipStream_t s) {
+namespace {
+template <class ST>
+hipError_t row_inv_z_t(const void* zbuf, const ZChunk& zc, int nx, int ny, int mx, size_t zplane,
+                       float scale, const float* dyn_inv, const float2* tw, hipStream_t s) {
+    using SE = typename ST::E;
     OutTable t;
     for (int k = 0; k < kZChunk; ++k) t.out[k] = k < zc.nz ? zc.out[k] : nullptr;
     const bool half = (mx == 2 * nx);
@@ -241,38 +250,86 @@ hipError_t launch_row_inv_z(const float2* zbuf, const ZChunk& zc, int nx, int ny
         using C = ColCfg<MM>;
         const int items = (ny + C::COLS - 1) / C::COLS * zc.nz;
         if (half) {
-            auto k = k_row_inv_t<MM, true, OutTable>;
+            auto k = k_row_inv_t<MM, true, OutTable, ST>;
             const int g = resident_blocks(k, C::THREADS, items);
-            hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, zbuf, t, nx, ny, zc.nz, zplane,
-                               scale, tw);
+            hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, (const SE*)zbuf, t, nx, ny,
+                               zc.nz, zplane, scale, dyn_inv, tw);
+        } else if constexpr (std::is_same_v<ST, StF32>) {
+            hipLaunchKernelGGL((k_row_inv_t<MM, false, OutTable, ST>), dim3(items),
+                               dim3(C::THREADS), 0, s, (const SE*)zbuf, t, nx, ny, zc.nz, zplane,
+                               scale, dyn_inv, tw);
         } else {
-            hipLaunchKernelGGL((k_row_inv_t<MM, false, OutTable>), dim3(items), dim3(C::THREADS),
-                               0, s, zbuf, t, nx, ny, zc.nz, zplane, scale, tw);
+            return hipErrorInvalidValue;
         }
     });
     return hipGetLastError();
 }
 
-template <class ZH>
-static hipError_t launch_col_z_asm_impl(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                                        size_t zplane, const ZSetAsm<ZH>& zs, const float2* tw,
-                                        hipStream_t s) {
+template <class ZH, class ST>
+hipError_t col_z_asm_t(const void* spec, void* zbuf, int ny, int my, int mx, size_t zplane,
+                       const ZSetAsm<ZH>& zs, float hscale, const float2* tw, hipStream_t s) {
+    using SE = typename ST::E;
     const bool half = (my == 2 * ny);
     CWO_DISPATCH_M(my, {
         using C = ZColCfg<MM>;
         dim3 grid((mx + C::COLS - 1) / C::COLS);
         if (half)
-            hipLaunchKernelGGL((k_col_z_asm<MM, true, ZH>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
+            hipLaunchKernelGGL((k_col_z_asm<MM, true, ZH, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
+        else if constexpr (std::is_same_v<ST, StF32>)
+            hipLaunchKernelGGL((k_col_z_asm<MM, false, ZH, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
         else
-            hipLaunchKernelGGL((k_col_z_asm<MM, false, ZH>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
+            return hipErrorInvalidValue;
     });
     return hipGetLastError();
 }
 
-hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                            size_t zplane, const AsmScalars& a, const ZChunk& zc,
+template <class ST>
+hipError_t col_z_fresnel_t(const void* spec, void* zbuf, int ny, int my, int mx, size_t zplane,
+                           const ZSetFresnel& zs, float hscale, const float2* tw, hipStream_t s) {
+    using SE = typename ST::E;
+    const bool half = (my == 2 * ny);
+    CWO_DISPATCH_M(my, {
+        using C = ZColCfg<MM>;
+        dim3 grid((mx + C::COLS - 1) / C::COLS);
+        if (half)
+            hipLaunchKernelGGL((k_col_z_fresnel<MM, true, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
+        else if constexpr (std::is_same_v<ST, StF32>)
+            hipLaunchKernelGGL((k_col_z_fresnel<MM, false, ST>), grid, dim3(C::THREADS), 0, s,
+                               (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
+        else
+            return hipErrorInvalidValue;
+    });
+    return hipGetLastError();
+}
+
+template <class ZH>
+hipError_t col_z_asm_prec(const void* spec, void* zbuf, int ny, int my, int mx, size_t zplane,
+                          const ZSetAsm<ZH>& zs, const Storage& st, const float2* tw,
+                          hipStream_t s) {
+    switch (st.prec) {
+        case 0: return col_z_asm_t<ZH, StF32>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+        case 1: return col_z_asm_t<ZH, StF16>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+        case 2: return col_z_asm_t<ZH, StBF16>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_row_inv_z(const void* zbuf, const ZChunk& zc, int nx, int ny, int mx,
+                            size_t zplane, const Storage& st, const float2* tw, hipStream_t s) {
+    switch (st.prec) {
+        case 0: return row_inv_z_t<StF32>(zbuf, zc, nx, ny, mx, zplane, st.out_scale, st.dyn_inv, tw, s);
+        case 1: return row_inv_z_t<StF16>(zbuf, zc, nx, ny, mx, zplane, st.out_scale, st.dyn_inv, tw, s);
+        case 2: return row_inv_z_t<StBF16>(zbuf, zc, nx, ny, mx, zplane, st.out_scale, st.dyn_inv, tw, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_col_z_asm(const void* spec, void* zbuf, int ny, int my, int mx, size_t zplane,
+                            const AsmScalars& a, const ZChunk& zc, const Storage& st,
                             const float2* tw, hipStream_t s) {
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
     if (sx * sx + sy * sy <= kAsmFastMaxS) {
@@ -280,31 +337,25 @@ hipError_t launch_col_z_asm(const float2* spec, float2* zbuf, int ny, int my, in
         zs.h = AsmZFast{a.lam * a.dfx, a.lam * a.dfy, mx, my};
         for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
         zs.nz = zc.nz;
-        return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
+        return col_z_asm_prec(spec, zbuf, ny, my, mx, zplane, zs, st, tw, s);
     }
     ZSetAsm<AsmZExact> zs;
     zs.h = AsmZExact{a.dfx, a.dfy, a.lam, mx, my};
     for (int k = 0; k < kZChunk; ++k) zs.zl[k] = k < zc.nz ? zc.zl[k] : 0.0;
     zs.nz = zc.nz;
-    return launch_col_z_asm_impl(spec, zbuf, ny, my, mx, zplane, zs, tw, s);
+    return col_z_asm_prec(spec, zbuf, ny, my, mx, zplane, zs, st, tw, s);
 }
 
-hipError_t launch_col_z_fresnel(const float2* spec, float2* zbuf, int ny, int my, int mx,
-                                size_t zplane, const float2* h, int nz, const float2* tw,
-                                hipStream_t s) {
-    ZSetFresnel zs{h, (size_t)(mx + my), mx, nz};
-    const bool half = (my == 2 * ny);
-    CWO_DISPATCH_M(my, {
-        using C = ZColCfg<MM>;
-        dim3 grid((mx + C::COLS - 1) / C::COLS);
-        if (half)
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, true>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-        else
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, false>), grid, dim3(C::THREADS), 0, s, spec,
-                               zbuf, ny, mx, zplane, zs, tw);
-    });
-    return hipGetLastError();
+hipError_t launch_col_z_fresnel(const void* spec, void* zbuf, int ny, int my, int mx,
+                                size_t zplane, const float2* h, int nz, const Storage& st,
+                                const float2* tw, hipStream_t s) {
+    const ZSetFresnel zs{h, (size_t)(mx + my), mx, nz};
+    switch (st.prec) {
+        case 0: return col_z_fresnel_t<StF32>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+        case 1: return col_z_fresnel_t<StF16>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+        case 2: return col_z_fresnel_t<StBF16>(spec, zbuf, ny, my, mx, zplane, zs, st.col_scale, tw, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace cwo

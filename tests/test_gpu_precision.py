@@ -82,3 +82,33 @@ def test_zero_field_f16(ctx):
     u = np.zeros((64, 64), dtype=np.complex64)
     y = run(ctx, D.ASM, u, 10e-6, 633e-9, 0.1, "f16")
     assert np.all(y == 0)
+
+
+@pytest.mark.parametrize("prec,kind,n", [("f16", D.ASM, 512), ("bf16", D.FRESNEL, 512),
+                                         ("f16", D.FRESNEL, 1024), ("bf16", D.ASM, 256)])
+def test_zstack_16bit_storage(ctx, prec, kind, n):
+    """z-stack with 16-bit storage of the shared spectrum and of the chunk's planes: each
+    plane within the 16-bit bound (3e-3 relative L2) of the FP64 oracle; the stack's planes
+    and the single 16-bit propagations store the same values twice each, so they agree to
+    about the same size of error."""
+    import torch
+    u = W.uniform_random_field(n, 700 + n)
+    if prec == "f16":
+        u = (u * np.float32(3e4)).astype(np.complex64)  # range scaling is needed for FP16
+    zs = [0.02, 0.05, -0.08, 0.11, 0.2]
+    note("zstack %s %s n=%d nz=%d" % (prec, kind, n, len(zs)))
+    t = torch.from_numpy(u).cuda()
+    stack = ctx.zstack(t, zs, 8e-6, 8e-6, 532e-9, kind=kind, precision=prec)
+    torch.cuda.synchronize()
+    fn = ctx.asm if kind == D.ASM else ctx.fresnel
+    for k, z in enumerate(zs):
+        y = stack[k].cpu().numpy()
+        assert np.all(np.isfinite(y))
+        ref = D.propagate(u, kind, 8e-6, 8e-6, 532e-9, z)
+        rl = D.rel_l2(y, ref)
+        one = fn(t, 8e-6, 8e-6, 532e-9, z, precision=prec).cpu().numpy()
+        d = D.rel_l2(y, one.astype(np.complex128))
+        note("zstack %s %s n=%d z=%g: rel_l2 vs oracle %.3e, vs single call %.3e"
+             % (prec, kind, n, z, rl, d))
+        assert rl <= 3e-3
+        assert d <= 3e-3
