@@ -224,8 +224,8 @@ typedef struct {
     double cy, wy; /* band-limit centre and full width along y [1/m] */
 } cwo_shift;
 
-/* Shifted angular spectrum propagation; same layout and scratch as cwo_asm. Complex64
- * storage only (other precisions: CWO_ERR_UNSUPPORTED). A null or non-finite shift is
+/* Shifted angular spectrum propagation; same layout, scratch and storage precisions as
+ * cwo_asm (16-bit storage in the padded form). A null or non-finite shift is
  * CWO_ERR_INVALID. */
 cwo_status cwo_asm_shifted(cwo_ctx* ctx, const cwo_params* p, const cwo_shift* shift,
                            const void* in, void* out, void* hip_stream);

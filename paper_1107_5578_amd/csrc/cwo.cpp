@@ -583,8 +583,8 @@ cwo_status propagate_locked(cwo_ctx* c, Workspace& ws, const cwo_params* p, int 
         float* masks = (float*)ensure(c, ws, ws.fourier, sizeof(float) * (size_t)(g.mx + g.my), &st);
         if (!masks) return st;
         CWO_HIP(c, timed(c, CWO_STAGE_COL, s, [&] {
-                    return cwo::launch_col_asm_shifted((float2*)buf, g.ny, g.my, g.mx, a, *shift,
-                                                       masks, twy, s, sto.layout);
+                    return cwo::launch_col_asm_shifted(buf, g.ny, g.my, g.mx, a, *shift, masks,
+                                                       sto, twy, s);
                 }));
     } else if (kind == CWO_ANGULAR) {
         const cwo::AsmScalars a = asm_scalars(p, g, p->z);
@@ -1667,7 +1667,6 @@ cwo_status cwo_asm_shifted(cwo_ctx* c, const cwo_params* p, const cwo_shift* sh,
         if (!std::isfinite(v)) return CWO_ERR_INVALID;
     cwo_status st = validate(p, CWO_ANGULAR, true);
     if (st != CWO_OK) return st;
-    if (p->precision != CWO_PREC_F32) return CWO_ERR_UNSUPPORTED;
     const cwo::AsmShift shift{sh->ox, sh->oy, sh->cx, sh->wx, sh->cy, sh->wy};
     return propagate(c, p, CWO_ANGULAR, in, out, stream, &shift);
 }

@@ -75,11 +75,11 @@ hipError_t launch_row_fwd(const float2* in, void* out, int nx, int ny, int mx, i
                           hipStream_t s);
 hipError_t launch_col_asm(void* buf, int ny, int my, int mx, int batch, size_t plane,
                           const AsmScalars& a, const Storage& st, const float2* tw, hipStream_t s);
-// Column pass of the shifted angular spectrum method (complex64 storage only); masks:
-// mx + my floats of scratch for the band masks.
-hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const AsmScalars& a,
-                                  const AsmShift& sh, float* masks, const float2* tw,
-                                  hipStream_t s, int layout = 0);
+// Column pass of the shifted angular spectrum method, buf in the storage and layout of st;
+// masks: mx + my floats of scratch for the band masks.
+hipError_t launch_col_asm_shifted(void* buf, int ny, int my, int mx, const AsmScalars& a,
+                                  const AsmShift& sh, float* masks, const Storage& st,
+                                  const float2* tw, hipStream_t s);
 hipError_t launch_col_fresnel(void* buf, int ny, int my, int mx, int batch, size_t plane,
                               const float2* hx, const float2* hy, const Storage& st,
                               const float2* tw, hipStream_t s);

@@ -106,9 +106,10 @@ struct ShiftedFast {
     }
 };
 
-template <class HF>
-static hipError_t launch_shifted_t(float2* buf, int ny, int my, int mx, const HF& hf,
+template <class HF, class ST>
+static hipError_t launch_shifted_t(void* buf, int ny, int my, int mx, const HF& hf, float hscale,
                                    const float2* tw, hipStream_t s, int layout) {
+    using SE = typename ST::E;
     const bool half = (my == 2 * ny);
     if (layout == 1 && (!half || mx % kTileW != 0)) return hipErrorInvalidValue;
     CWO_DISPATCH_M(my, {
@@ -116,25 +117,40 @@ static hipError_t launch_shifted_t(float2* buf, int ny, int my, int mx, const HF
         const int items = (mx + C::COLS - 1) / C::COLS;
         if (half && layout == 1) {
             if constexpr (MM == 8192)  // two transforms of 4096 per column, one per block
-                hipLaunchKernelGGL((k_col_split<MM / 2, HF, StF32, LayTile>), dim3(mx), dim3(MM / 32),
-                                   0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayTile{ny});
-            else
-                hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayTile>), dim3(items),
-                                   dim3(C::THREADS), 0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw,
+                hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx), dim3(MM / 32),
+                                   0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw,
                                    LayTile{ny});
-        } else if (half)
-            hipLaunchKernelGGL((k_col<MM, true, HF, StF32, LayRow>), dim3(items), dim3(C::THREADS),
-                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayRow{mx});
-        else
-            hipLaunchKernelGGL((k_col<MM, false, HF, StF32, LayRow>), dim3(items), dim3(C::THREADS),
-                               0, s, buf, ny, mx, 1, (size_t)0, hf, 1.0f, tw, LayRow{mx});
+            else
+                hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items),
+                                   dim3(C::THREADS), 0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf,
+                                   hscale, tw, LayTile{ny});
+        } else if (half) {
+            hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
+                               0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw, LayRow{mx});
+        } else if constexpr (std::is_same_v<ST, StF32>) {
+            hipLaunchKernelGGL((k_col<MM, false, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
+                               0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw, LayRow{mx});
+        } else {
+            return hipErrorInvalidValue;
+        }
     });
     return hipGetLastError();
 }
 
-hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const AsmScalars& a,
-                                  const AsmShift& sh, float* masks, const float2* tw,
-                                  hipStream_t s, int layout) {
+template <class HF>
+static hipError_t launch_shifted_prec(void* buf, int ny, int my, int mx, const HF& hf,
+                                      const Storage& st, const float2* tw, hipStream_t s) {
+    switch (st.prec) {
+        case 0: return launch_shifted_t<HF, StF32>(buf, ny, my, mx, hf, st.col_scale, tw, s, st.layout);
+        case 1: return launch_shifted_t<HF, StF16>(buf, ny, my, mx, hf, st.col_scale, tw, s, st.layout);
+        case 2: return launch_shifted_t<HF, StBF16>(buf, ny, my, mx, hf, st.col_scale, tw, s, st.layout);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_col_asm_shifted(void* buf, int ny, int my, int mx, const AsmScalars& a,
+                                  const AsmShift& sh, float* masks, const Storage& st,
+                                  const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL(k_band_masks, dim3((mx + my + 255) / 256), dim3(256), 0, s, masks, mx, my,
                        a.dfx, a.dfy, sh);
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
@@ -153,10 +169,10 @@ hipError_t launch_col_asm_shifted(float2* buf, int ny, int my, int mx, const Asm
         hf.mask = masks;
         hf.mx = mx;
         hf.my = my;
-        return launch_shifted_t(buf, ny, my, mx, hf, tw, s, layout);
+        return launch_shifted_prec(buf, ny, my, mx, hf, st, tw, s);
     }
     ShiftedH<AsmH> hf{AsmH{a.dfx, a.dfy, a.lam, a.zl, mx, my}, a.dfx, a.dfy, sh, masks, mx, my};
-    return launch_shifted_t(buf, ny, my, mx, hf, tw, s, layout);
+    return launch_shifted_prec(buf, ny, my, mx, hf, st, tw, s);
 }
 
 }  // namespace cwo

@@ -468,7 +468,8 @@ class Context:
                          oz, out, stream, True)
 
     def asm_shifted(self, u, dx=10e-6, dy=None, wavelength=633e-9, z=0.1, ox=0.0, oy=0.0,
-                    cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None):
+                    cx=0.0, wx=0.0, cy=0.0, wy=0.0, nopad=False, out=None, stream=None,
+                    precision="f32"):
         """Shifted angular spectrum propagation: window offset (ox, oy) [m], band limits
         Rect((fx - cx)/wx) Rect((fy - cy)/wy) [1/m] (a width <= 0: no limit)."""
         sh = Shift(float(ox), float(oy), float(cx), float(wx), float(cy), float(wy))
@@ -478,7 +479,7 @@ class Context:
             return lib.cwo_asm_shifted(h, pp, ctypes.byref(sh), a, b, s)
 
         call.__name__ = "cwo_asm_shifted"
-        return self._propagate(call, ANGULAR, u, dx, dy, wavelength, z, "f32", nopad, out,
+        return self._propagate(call, ANGULAR, u, dx, dy, wavelength, z, precision, nopad, out,
                                stream)
 
 

@@ -150,7 +150,8 @@ def test_shifted_errors(ctx):
     with pytest.raises(cwo.CwoError) as e:
         ctx.asm_shifted(t, 8e-6, 8e-6, 532e-9, 0.2, ox=math.nan)
     assert e.value.status == cwo.CWO_ERR_INVALID
-    p = cwo.make_params(64, 64, 8e-6, z=0.2, precision="f16")
+    # 16-bit storage needs the padded form
+    p = cwo.make_params(64, 64, 8e-6, z=0.2, precision="f16", nopad=True)
     sh = cwo.Shift()
     out = torch.empty_like(t)
     import ctypes
@@ -158,3 +159,22 @@ def test_shifted_errors(ctx):
                                   ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   None)
     assert st == cwo.CWO_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,n", [("f16", 512), ("bf16", 2048)])
+def test_shifted_16bit_storage(ctx, prec, n):
+    # shifted, band-limited ASM with FP16 / BF16 storage of the padded planes: within the
+    # 16-bit bound (3e-3 relative L2) of the FP64 oracle (2048^2: the tiled plane)
+    import torch
+    u = W.uniform_random_field(n, 48 + n)
+    z = 1.5
+    wx = S.band_limit(n, 8e-6, 532e-9, z)
+    note("shifted %d %s z=%g band=%g" % (n, prec, z, wx))
+    t = torch.from_numpy(u).cuda()
+    y = ctx.asm_shifted(t, 8e-6, 8e-6, 532e-9, z, 0.4e-3, -0.3e-3, 0.0, wx, 0.0, wx,
+                        precision=prec)
+    torch.cuda.synchronize()
+    ref = S.propagate(u, 8e-6, 8e-6, 532e-9, z, 0.4e-3, -0.3e-3, 0.0, wx, 0.0, wx)
+    rl = D.rel_l2(y.cpu().numpy(), ref)
+    note("shifted %d %s rel_l2=%.3e" % (n, prec, rl))
+    assert np.all(np.isfinite(y.cpu().numpy())) and rl <= 3e-3
