@@ -19,7 +19,7 @@ It follows the paper's definitions, in the paper's order and notation:
   extract the N x N result afterwards (Sec. 2.1.6), so the circular
   convolution does not alias.
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
 
 * The field sits at the top-left of the padded grid and the result is cropped
   from the top-left (a circular shift commutes with the circular convolution,

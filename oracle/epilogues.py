@@ -10,7 +10,7 @@ may import this module; it shares nothing with the product library.
 * Complex (Sec. 7.1): a phase field back to a complex field, A exp(i phi) (A = 1 for a
   kinoform).
 
-Readings (listed in DESIGN.md):
+Readings:
 
 * The epilogues run on complex64 fields in FP32: I = re*re + im*im, and Eq. norm
   evaluated in the order it is written, (I - min), then / (max - min), then * top, each

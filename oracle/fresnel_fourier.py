@@ -12,7 +12,7 @@ Fresnel integral gives one Fourier transform of the field times a chirp,
 
 on N x N samples without padding (one FFT, Table of diffraction classes).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 
 * Sample positions are centred: array index j is coordinate (j - N/2) * pitch on
   both planes (the paper's index range -N/2 <= m < N/2).

@@ -14,7 +14,7 @@ plane:
 (k = 2 pi/lambda; pi r^2/(lambda z_j) is the paper's (2 pi/lambda) r^2/(2 z_j)). Both are
 O(N Nx Ny) sums with no transform; the oracle evaluates them term by term.
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 
 * The printed exponent of the field lacks the imaginary unit; the Fresnel wavelet
   exp(+i pi r^2/(lambda z_j)) is meant (the sign of the convolution form's impulse

@@ -12,7 +12,7 @@ and the product masked by the band-limit functions Rect((fx - cx)/wx) and
 Rect((fy - cy)/wy). The padding, frequency grid, normalisation and crop are those
 of the plain method (``oracle.diffraction``).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 
 * Eq. shift_ang2 prints the exponent without the imaginary unit; a linear phase
   exp(+i*2*pi*(Ox*fx + Oy*fy)) is taken. It moves the destination window: output

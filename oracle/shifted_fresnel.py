@@ -16,7 +16,7 @@ h[m, n] = exp(i pi (Sx m^2 + Sy n^2)), Sx = px0 px1/(lambda z)). That route reac
 this sum exactly up to rounding, so the oracle is the sum itself: the kernel separates
 into x and y factors and the sum is two matrix products.
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 
 * Indices are centred, m = j - N/2 for array index j, on both planes (the paper's
   range -N/2 <= m < N/2); so (Ox0, Oy0) and (Ox1, Oy1) are the window centres.
