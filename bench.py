@@ -250,10 +250,11 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
     z ~ U[0.01, 1] m, wavelength in {473, 532, 633} nm, 8 um pitch) through cwo_submit /
     cwo_poll under an HBM budget. Every request reads a field of its own: 10k distinct
     fields do not fit, so each size has a ring of FIELD_RING distinct seeded fields and
-    successive requests of one size take successive fields (no two neighbouring requests
-    share an input, so none of them can be merged into a z-stack). Outputs rotate through a
-    ring per size (a buffer is reused only after its previous request is done)."""
-    FIELD_RING = 4
+    successive requests of one size take successive fields. A serving batch takes at most 8
+    consecutive requests, so with a ring of 8 no batch holds two requests on one field and
+    none can be merged into a z-stack. Outputs rotate through a ring per size (a buffer is
+    reused only after its previous request is done)."""
+    FIELD_RING = 8
     reqs = W.serving_requests(count, 1.0, seed=5)
     sizes = sorted({r.n for r in reqs})
     fields = {n: [torch.from_numpy(W.uniform_random_field(n, 5000 + FIELD_RING * k + i)).to(dev)
@@ -313,9 +314,9 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
     cap = closed["req_per_s"]
     out = {"workload": "%d requests, sizes %s^2 uniform, ASM/Fresnel 50/50, z~U[0.01,1] m, "
                        "lambda in {473,532,633} nm, 8 um, HBM budget %d GiB, a ring of %d "
-                       "distinct fields per size (no two successive requests of a size share "
-                       "an input)" % (count, "/".join(str(n) for n in sizes), budget >> 30,
-                                      FIELD_RING),
+                       "distinct fields per size (no serving batch holds two requests on one "
+                       "field)" % (count, "/".join(str(n) for n in sizes), budget >> 30,
+                                   FIELD_RING),
            "plain_per_call_req_per_s": round(plain_rps, 1),
            "closed_loop": closed, "served_vs_plain": round(cap / plain_rps, 3), "open_loop": {}}
     for f in rates:
