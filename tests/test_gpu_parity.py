@@ -192,6 +192,17 @@ def test_fresnel_4096(ctx):
     check(y, ref, label="fresnel-4096")
 
 
+def test_exact_phase_4096(ctx):
+    # a 0.3 um pitch at 633 nm puts most of the padded grid beyond s = 0.05 and its edges
+    # beyond s = 1 ((lambda/2dx)^2 = 1.11 per axis): the FP64 per-bin transfer function with
+    # evanescent bins, on the split column pass
+    u = W.uniform_random_field(4096, 46)
+    note("asm exact phase 4096")
+    y = gpu_run(ctx, D.ASM, u, 0.3e-6, 0.3e-6, 633e-9, 1e-4)
+    ref = D.asm(u, 0.3e-6, 0.3e-6, 633e-9, 1e-4)
+    check(y, ref, label="asm-exact-4096")
+
+
 @pytest.mark.parametrize("kind", [D.ASM, D.FRESNEL])
 def test_4096_layouts_agree(ctx, kind):
     """The row-major and the tiled (split-transform) plane at 4096^2 compute the same
