@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 clocks (one per
+# clock per CU) at 2.4 GHz
+VALU_PEAK_GWAVE = 256 * 2.4
 
 # algorithmic bytes per launch of each kernel for an N x N field, M = 2N, complex64
 # intermediates: row_fwd reads the field and writes the N x M spectrum rows; col reads
@@ -50,8 +53,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+def committed_record(kernel: str):
+    """The committed rocprofv3 counter record of a kernel of the 2048^2 plane, if it was
     taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_asm2048.json" % kernel)
     if not os.path.exists(path):
@@ -60,7 +63,13 @@ def committed_traffic(kernel: str):
         rec = json.load(f)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def committed_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter record, or None."""
+    rec = committed_record(kernel)
+    return rec.get("bytes_per_launch") if rec else None
 
 
 def host_cpu_model() -> str:
@@ -441,6 +450,16 @@ def main():
                 "traffic": traffic,
                 "plane_alg_bytes": sum(sb.values()),
                 "plane_GBps": round(sum(sb.values()) / (ms_per_step * 1e-3) / 1e9, 1)}
+    # the same kernel against the vector-issue peak: its committed SQ_INSTS_VALU count per
+    # launch (wave instructions, same source hash) over its live average duration; one wave
+    # instruction per clock per CU is the peak (packed FP32 is not used)
+    rec = committed_record(dominant) if n == cfg.n and args.kind == "asm" else None
+    if rec and rec.get("valu_wave_instructions"):
+        achieved = rec["valu_wave_instructions"] / (d["avg_us"] * 1e-6)
+        roofline["issue"] = {"bound": "alu", "achieved": round(achieved / 1e9, 1),
+                             "peak": VALU_PEAK_GWAVE, "unit": "G wave-instructions/s",
+                             "frac": round(achieved / 1e9 / VALU_PEAK_GWAVE, 4),
+                             "valu_wave_instructions": rec["valu_wave_instructions"]}
 
     batched = None
     if not args.no_batched and args.kind == "asm" and args.precision == "f32":
