@@ -249,11 +249,19 @@ struct TwCache {
     }
 };
 
-// LDS slot of element e: one pad slot every 16 elements keeps the strided
-// Stockham writes spread over the banks
-__device__ __forceinline__ int lds_slot(int e) { return e + (e >> 4); }
+// LDS slot of element e of a length-M exchange. The strided Stockham writes (16 apart in
+// the first pass) are spread over the banks either by one pad slot every 16 elements, or,
+// for M = 4096, by XOR-ing the element's low 4 bits with the next 4 (a permutation within
+// each aligned group of 16 slots, so no padding). Measured: on the 2048^2 plane the column
+// pass takes 61.3 instead of 63.0 us with the row passes unchanged, the 4096^2 plane is
+// unchanged overall, and at other lengths the padding is as fast or faster.
 template <int M>
-constexpr int lds_elems() { return M + M / 16; }
+__device__ __forceinline__ int lds_slot(int e) {
+    if constexpr (M == 4096) return e ^ ((e >> 4) & 15);
+    else return e + (e >> 4);
+}
+template <int M>
+constexpr int lds_elems() { return M == 4096 ? M : M + M / 16; }
 
 // Block barrier for the LDS exchanges only. Threads of a block communicate through
 // LDS alone (every global location is written by exactly one thread), so the
@@ -331,7 +339,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
             const int base = (b / NS) * NS * RP + k;
 #pragma unroll
             for (int kk = 0; kk < RP; ++kk) {
-                lds[lds_slot(base + kk * NS)] = u[0][kk];
+                lds[lds_slot<M>(base + kk * NS)] = u[0][kk];
                 held[i * RP + kk] = u[1][kk];
             }
         } else {
@@ -341,7 +349,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[P][E], float2* lds, in
                 float2 x[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) x[p] = u[p][kk];
-                lds_put<P>(lds, lds_slot(base + kk * NS), x);
+                lds_put<P>(lds, lds_slot<M>(base + kk * NS), x);
             }
         }
     }
@@ -381,7 +389,7 @@ __device__ __forceinline__ void fft_impl(float2 (&v)[P][E], float2* lds, int j,
                  if constexpr (SPLIT) {
                      lds_barrier();
 #pragma unroll
-                     for (int r = 0; r < E; ++r) v[0][r] = lds[lds_slot(j + r * T)];
+                     for (int r = 0; r < E; ++r) v[0][r] = lds[lds_slot<M>(j + r * T)];
                      lds_barrier();
                      constexpr int NB = E / RP;
 #pragma unroll
@@ -390,18 +398,18 @@ __device__ __forceinline__ void fft_impl(float2 (&v)[P][E], float2* lds, int j,
                          const int k = b & (NS - 1);
                          const int base = (b / NS) * NS * RP + k;
 #pragma unroll
-                         for (int kk = 0; kk < RP; ++kk) lds[lds_slot(base + kk * NS)] = held[i * RP + kk];
+                         for (int kk = 0; kk < RP; ++kk) lds[lds_slot<M>(base + kk * NS)] = held[i * RP + kk];
                      }
                      lds_barrier();
 #pragma unroll
-                     for (int r = 0; r < E; ++r) v[P - 1][r] = lds[lds_slot(j + r * T)];
+                     for (int r = 0; r < E; ++r) v[P - 1][r] = lds[lds_slot<M>(j + r * T)];
                      lds_barrier();
                  } else {
                      lds_barrier();
 #pragma unroll
                      for (int r = 0; r < E; ++r) {
                          float2 x[P];
-                         lds_get<P>(lds, lds_slot(j + r * T), x);
+                         lds_get<P>(lds, lds_slot<M>(j + r * T), x);
 #pragma unroll
                          for (int q = 0; q < P; ++q) v[q][r] = x[q];
                      }
