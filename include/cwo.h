@@ -415,10 +415,11 @@ typedef enum {
     CWO_STAGE_COUNT = 8
 } cwo_stage;
 
-/* Per-kernel timing for benchmarks. enable != 0 clears the totals and brackets every
- * kernel the context launches afterwards with HIP events on the launch stream; 0 stops.
- * cwo_profile_read waits for the recorded events and returns the summed milliseconds and
- * the number of launches of one stage. */
+/* Per-kernel timing for benchmarks. enable != 0 clears the totals and times every stage
+ * the context runs afterwards with a pair of HIP events that the runtime stamps from the
+ * stage's kernels themselves (the first kernel's start, the last kernel's end; no extra
+ * packets enter the stream); 0 stops. cwo_profile_read waits for the recorded events and
+ * returns the summed milliseconds and the number of timed launches of one stage. */
 cwo_status cwo_profile(cwo_ctx* ctx, int32_t enable);
 cwo_status cwo_profile_read(cwo_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
 

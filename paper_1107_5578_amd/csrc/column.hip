@@ -25,24 +25,24 @@ static hipError_t launch_col_t(void* buf, int ny, int my, int mx, int batch, siz
             const bool split = MM == 8192 ? col_form != 1 : col_form == 2;
             if (split) {
                 if constexpr (CAN_SPLIT)
-                    hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx * batch),
+                    launch_kernel((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx * batch),
                                        dim3(MM / 32), 0, s, (SE*)buf, ny, mx, batch, plane, hf,
                                        hscale, tw, LayTile{ny});
                 else
                     return hipErrorInvalidValue;
             } else {
                 if constexpr (CAN_FULL)
-                    hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items),
+                    launch_kernel((k_col<MM, true, HF, ST, LayTile>), dim3(items),
                                        dim3(C::THREADS), 0, s, (SE*)buf, ny, mx, batch, plane, hf,
                                        hscale, tw, LayTile{ny});
                 else
                     return hipErrorInvalidValue;
             }
         } else if (half) {
-            hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS), 0,
+            launch_kernel((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS), 0,
                                s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw, LayRow{mx});
         } else if constexpr (std::is_same_v<ST, StF32>) {
-            hipLaunchKernelGGL((k_col<MM, false, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
+            launch_kernel((k_col<MM, false, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
                                0, s, (SE*)buf, ny, mx, batch, plane, hf, hscale, tw, LayRow{mx});
         } else {
             return hipErrorInvalidValue;

@@ -155,6 +155,10 @@ struct cwo_ctx {
     std::map<TuneKey, cwo_tuning> tuned;
 };
 
+namespace cwo {
+thread_local StageTimer* g_stage_timer = nullptr;
+}
+
 namespace {
 
 cwo_status dev_fail(cwo_ctx* c) {
@@ -173,16 +177,24 @@ hipEvent_t take_event(cwo_ctx* c) {
     return e;
 }
 
-// Launch through `fn` (returning hipError_t); with profiling on, bracket it with events.
+// Launch through `fn` (returning hipError_t); with profiling on, the stage's kernels stamp
+// a pair of events with their own start and end (a stage that launched nothing records
+// nothing).
 template <class F>
-hipError_t timed(cwo_ctx* c, int stage, hipStream_t s, F&& fn) {
+hipError_t timed(cwo_ctx* c, int stage, hipStream_t, F&& fn) {
     if (!c->profiling) return fn();
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, s);
-    if (e == hipSuccess) e = fn();
-    if (e == hipSuccess) e = hipEventRecord(b, s);
-    c->recs.push_back({stage, a, b});
+    cwo::StageTimer t{a, b, false};
+    cwo::g_stage_timer = &t;
+    const hipError_t e = fn();
+    cwo::g_stage_timer = nullptr;
+    if (t.started) {
+        c->recs.push_back({stage, a, b});
+    } else {
+        c->spare.push_back(a);
+        c->spare.push_back(b);
+    }
     return e;
 }
 

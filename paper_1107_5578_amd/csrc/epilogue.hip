@@ -127,17 +127,17 @@ static unsigned epi_grid(size_t n) {
 }
 
 hipError_t launch_intensity(const float2* in, float* out, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_intensity, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, out, n);
+    launch_kernel(k_intensity, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, out, n);
     return hipGetLastError();
 }
 
 hipError_t launch_phase(const float2* in, float* out, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_phase, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, out, n);
+    launch_kernel(k_phase, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, out, n);
     return hipGetLastError();
 }
 
 hipError_t launch_polar(const float* phi, const float* amp, float2* out, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_polar, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, phi, amp, out, n);
+    launch_kernel(k_polar, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, phi, amp, out, n);
     return hipGetLastError();
 }
 
@@ -145,13 +145,13 @@ hipError_t launch_scale(const float* in, size_t n, float top, bool u8, void* out
                         hipStream_t s) {
     const unsigned nb = epi_grid(n) < (unsigned)kRangeBlocks ? epi_grid(n) : (unsigned)kRangeBlocks;
     float* part = work + 4;
-    hipLaunchKernelGGL(k_minmax_partial, dim3(nb), dim3(kEpiThreads), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(kEpiThreads), 0, s, part, (int)nb, top, work);
+    launch_kernel(k_minmax_partial, dim3(nb), dim3(kEpiThreads), 0, s, in, n, part);
+    launch_kernel(k_minmax_final, dim3(1), dim3(kEpiThreads), 0, s, part, (int)nb, top, work);
     if (u8)
-        hipLaunchKernelGGL(k_scale<true>, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, n,
+        launch_kernel(k_scale<true>, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, n,
                            (const float*)work, out);
     else
-        hipLaunchKernelGGL(k_scale<false>, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, n,
+        launch_kernel(k_scale<false>, dim3(epi_grid(n)), dim3(kEpiThreads), 0, s, in, n,
                            (const float*)work, out);
     return hipGetLastError();
 }

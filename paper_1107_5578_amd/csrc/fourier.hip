@@ -119,19 +119,19 @@ hipError_t launch_fresnel_fourier(const float2* in, float2* out, float2* tabs,
                                   const FourierPlan& fp, const float2* twx, const float2* twy,
                                   hipStream_t s) {
     const int len = fp.nx + fp.ny;
-    hipLaunchKernelGGL(k_ff_tables, dim3((2 * len + 255) / 256), dim3(256), 0, s, tabs, fp);
+    launch_kernel(k_ff_tables, dim3((2 * len + 255) / 256), dim3(256), 0, s, tabs, fp);
     const float2* prex = tabs;
     const float2* prey = tabs + fp.nx;
     const float2* postx = tabs + len;
     const float2* posty = tabs + len + fp.nx;
     CWO_DISPATCH_M(fp.nx, {
         using C = RowCfg<MM>;
-        hipLaunchKernelGGL((k_ff_row<MM>), dim3((fp.ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
+        launch_kernel((k_ff_row<MM>), dim3((fp.ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
                            0, s, in, out, fp.ny, prex, prey, twx);
     });
     CWO_DISPATCH_M(fp.ny, {
         using C = ColCfg<MM>;
-        hipLaunchKernelGGL((k_ff_col<MM>), dim3((fp.nx + C::COLS - 1) / C::COLS), dim3(C::THREADS),
+        launch_kernel((k_ff_col<MM>), dim3((fp.nx + C::COLS - 1) / C::COLS), dim3(C::THREADS),
                            0, s, out, fp.nx, postx, posty, twy);
     });
     return hipGetLastError();

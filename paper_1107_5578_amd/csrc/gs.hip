@@ -317,7 +317,7 @@ hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int 
                 using C = GsTileCfg<MM, RPB>;
                 if (ny % C::RPB != 0) return hipErrorInvalidValue;
                 auto k = k_row_gs_tile<MM, ST, RPB>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),
                                    dim3(C::THREADS), 0, s, (SE*)spec, amp, out, num, nx, ny,
                                    scale, dyn_inv, fwd_scale, dyn_fwd, tw);
             } else {
@@ -330,10 +330,10 @@ hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int 
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB);
         if (half)
-            hipLaunchKernelGGL((k_row_gs<MM, true, ST>), grid, dim3(C::THREADS), 0, s, (SE*)spec,
+            launch_kernel((k_row_gs<MM, true, ST>), grid, dim3(C::THREADS), 0, s, (SE*)spec,
                                amp, out, num, nx, ny, scale, dyn_inv, fwd_scale, dyn_fwd, tw);
         else
-            hipLaunchKernelGGL((k_row_gs<MM, false, ST>), grid, dim3(C::THREADS), 0, s, (SE*)spec,
+            launch_kernel((k_row_gs<MM, false, ST>), grid, dim3(C::THREADS), 0, s, (SE*)spec,
                                amp, out, num, nx, ny, scale, dyn_inv, fwd_scale, dyn_fwd, tw);
     });
     return hipGetLastError();
@@ -360,8 +360,8 @@ int gs_partials(int mx) { return gs_partials_per_row(mx); }
 
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
                             int nx, int ny, int mx, int iters, hipStream_t s) {
-    hipLaunchKernelGGL(k_gs_den, dim3(1), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
-    hipLaunchKernelGGL(k_gs_errors, dim3(iters), dim3(256), 0, s, num, (const double*)den_work,
+    launch_kernel(k_gs_den, dim3(1), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
+    launch_kernel(k_gs_errors, dim3(iters), dim3(256), 0, s, num, (const double*)den_work,
                        errors, ny * gs_partials_per_row(mx));
     return hipGetLastError();
 }

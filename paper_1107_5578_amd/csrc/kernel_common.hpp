@@ -9,10 +9,27 @@
 #include <type_traits>
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "fft_device.hpp"
 #include "launch.hpp"
 
 namespace cwo {
+
+// Every kernel of the library is launched through here: a plain launch, or with an armed
+// stage timer one whose start and stop events the runtime stamps from the kernel's own
+// execution (see StageTimer).
+template <class K, class... A>
+inline void launch_kernel(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t s,
+                          A... args) {
+    if (StageTimer* t = g_stage_timer) {
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, s,
+                              t->started ? nullptr : t->start, t->stop, 0u, args...);
+        t->started = true;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    }
+}
 
 // ---- configuration per transform length --------------------------------------
 

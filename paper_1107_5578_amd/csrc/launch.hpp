@@ -6,6 +6,17 @@
 
 namespace cwo {
 
+// Stage timing for benchmarks. While a timer is armed on the calling thread, every kernel
+// launch of the library stamps the timer's HIP events from the dispatch itself: the first
+// kernel of the stage its start, each kernel the stop (so the last one's end stays), and no
+// extra packets enter the stream between the kernels.
+struct StageTimer {
+    hipEvent_t start;
+    hipEvent_t stop;
+    bool started;  // a kernel has stamped `start`
+};
+extern thread_local StageTimer* g_stage_timer;
+
 // Per-launch FP64 scalars of the angular-spectrum transfer function.
 struct AsmScalars {
     double dfx, dfy;  // 1/(Mx dx), 1/(My dy)

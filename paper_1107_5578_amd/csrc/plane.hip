@@ -353,7 +353,7 @@ __global__ void k_twiddles(float2* tw, int m) {
 // ---- host launchers ------------------------------------------------------------
 
 hipError_t launch_twiddles(float2* tw, int m, hipStream_t s) {
-    hipLaunchKernelGGL(k_twiddles, dim3((m + 255) / 256), dim3(256), 0, s, tw, m);
+    launch_kernel(k_twiddles, dim3((m + 255) / 256), dim3(256), 0, s, tw, m);
     return hipGetLastError();
 }
 
@@ -372,13 +372,13 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
                 if ((ny * batch) % C::RPB != 0) return hipErrorInvalidValue;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_fwd_tsplit<MM / 2, 2, C::E, false, ST, IN>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
             } else if constexpr (MM >= 2048) {
                 using C = TileRowCfg<MM>;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_fwd_tile<MM, ST, IN>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
             } else {
                 return hipErrorInvalidValue;
@@ -394,7 +394,7 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
                 using C = RowCfg<MM>;
                 const int groups = (ny * batch + C::RPB - 1) / C::RPB;
                 auto k = k_row_fwd_pf<MM, true, ST, IN>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, ins, (SE*)out, nx, ny, batch, out_plane, sc, tw);
             }
         });
@@ -404,10 +404,10 @@ static hipError_t launch_row_fwd_t(const IN& ins, void* out, int nx, int ny, int
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
         if (half)
-            hipLaunchKernelGGL((k_row_fwd<MM, true, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
+            launch_kernel((k_row_fwd<MM, true, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
                                (SE*)out, nx, ny, out_plane, sc, tw);
         else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_row_fwd<MM, false, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
+            launch_kernel((k_row_fwd<MM, false, ST, IN>), grid, dim3(C::THREADS), 0, s, ins,
                                (SE*)out, nx, ny, out_plane, sc, tw);
         else
             return hipErrorInvalidValue;
@@ -461,14 +461,14 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
                 if ((ny * batch) % C::RPB != 0) return hipErrorInvalidValue;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_inv_tsplit<MM / 2, RPB, PF, !F32, OUT, ST>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
                                    dyn_inv, tw);
             } else if constexpr (MM >= 2048) {
                 using C = TileRowCfg<MM>;
                 const int groups = ny * batch / C::RPB;
                 auto k = k_row_inv_tile<MM, OUT, ST>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
                                    dyn_inv, tw);
             } else {
@@ -483,7 +483,7 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
                 using C = RowCfg<MM>;
                 const int groups = (ny * batch + C::RPB - 1) / C::RPB;
                 auto k = k_row_inv_pf<MM, true, OUT, ST>;
-                hipLaunchKernelGGL(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
+                launch_kernel(k, dim3(resident_blocks(k, C::THREADS, groups)), dim3(C::THREADS),
                                    0, s, (const SE*)in, outs, nx, ny, batch, in_plane, scale,
                                    dyn_inv, tw);
             }
@@ -494,10 +494,10 @@ static hipError_t launch_row_inv_t(const void* in, const OUT& outs, int nx, int 
         using C = RowCfg<MM>;
         dim3 grid((ny + C::RPB - 1) / C::RPB, batch);
         if (half)
-            hipLaunchKernelGGL((k_row_inv<MM, true, OUT, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_row_inv<MM, true, OUT, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)in, outs, nx, ny, in_plane, scale, dyn_inv, tw);
         else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_row_inv<MM, false, OUT, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_row_inv<MM, false, OUT, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)in, outs, nx, ny, in_plane, scale, dyn_inv, tw);
         else
             return hipErrorInvalidValue;
@@ -616,8 +616,8 @@ template <class T>
 hipError_t range_scale_t(const T* in, size_t n, float* work, hipStream_t s) {
     const size_t want = (n + 256 * 16 - 1) / (256 * 16);
     const int nb = want < 1 ? 1 : (want < (size_t)kRangeBlocks ? (int)want : kRangeBlocks);
-    hipLaunchKernelGGL((k_absmax_partial<T>), dim3(nb), dim3(256), 0, s, in, n, work + 2);
-    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, (const float*)(work + 2), nb, work);
+    launch_kernel((k_absmax_partial<T>), dim3(nb), dim3(256), 0, s, in, n, work + 2);
+    launch_kernel(k_absmax_final, dim3(1), dim3(256), 0, s, (const float*)(work + 2), nb, work);
     return hipGetLastError();
 }
 }  // namespace

@@ -102,15 +102,15 @@ hipError_t launch_pls(const float* points, int npts, void* work, void* out, bool
                       const PlsParams& pp, hipStream_t s) {
     PlsPoint* recs = static_cast<PlsPoint*>(work);
     if (npts > 0)
-        hipLaunchKernelGGL(k_pls_points, dim3((npts + 255) / 256), dim3(256), 0, s,
+        launch_kernel(k_pls_points, dim3((npts + 255) / 256), dim3(256), 0, s,
                            reinterpret_cast<const float4*>(points), npts, recs, pp.ox, pp.oy,
                            pp.oz, pp.lam);
     const dim3 grid((pp.nx + kPlsTile - 1) / kPlsTile, pp.ny);
     if (field)
-        hipLaunchKernelGGL(k_pls<true>, grid, dim3(kPlsThreads), 0, s, (const PlsPoint*)recs, npts,
+        launch_kernel(k_pls<true>, grid, dim3(kPlsThreads), 0, s, (const PlsPoint*)recs, npts,
                            out, pp.nx, pp.ny, pp.px, pp.py, pp.cre, pp.cim);
     else
-        hipLaunchKernelGGL(k_pls<false>, grid, dim3(kPlsThreads), 0, s, (const PlsPoint*)recs, npts,
+        launch_kernel(k_pls<false>, grid, dim3(kPlsThreads), 0, s, (const PlsPoint*)recs, npts,
                            out, pp.nx, pp.ny, pp.px, pp.py, pp.cre, pp.cim);
     return hipGetLastError();
 }

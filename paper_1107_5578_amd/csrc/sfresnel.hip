@@ -112,7 +112,7 @@ __global__ __launch_bounds__(RowCfg<M>::THREADS) void k_sf_row_inv(
 
 hipError_t launch_sf_tables(float2* tabs, const SfPlan& sp, hipStream_t s) {
     const int len = sp.nx + sp.ny;
-    hipLaunchKernelGGL(k_sf_tables, dim3((2 * len + 255) / 256), dim3(256), 0, s, tabs, sp);
+    launch_kernel(k_sf_tables, dim3((2 * len + 255) / 256), dim3(256), 0, s, tabs, sp);
     return hipGetLastError();
 }
 
@@ -121,7 +121,7 @@ hipError_t launch_sf_row_fwd(const float2* in, float2* out, int nx, int ny, cons
     const int mx = 2 * nx;
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
-        hipLaunchKernelGGL((k_sf_row_fwd<MM>), dim3((ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
+        launch_kernel((k_sf_row_fwd<MM>), dim3((ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
                            0, s, in, out, nx, ny, tabs, tabs + nx, tw);
     });
     return hipGetLastError();
@@ -134,7 +134,7 @@ hipError_t launch_sf_row_inv(const float2* in, float2* out, int nx, int ny, floa
     const float2* posty = postx + nx;
     CWO_DISPATCH_M(mx, {
         using C = RowCfg<MM>;
-        hipLaunchKernelGGL((k_sf_row_inv<MM>), dim3((ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
+        launch_kernel((k_sf_row_inv<MM>), dim3((ny + C::RPB - 1) / C::RPB), dim3(C::THREADS),
                            0, s, in, out, nx, ny, scale, postx, posty, tw);
     });
     return hipGetLastError();

@@ -117,18 +117,18 @@ static hipError_t launch_shifted_t(void* buf, int ny, int my, int mx, const HF& 
         const int items = (mx + C::COLS - 1) / C::COLS;
         if (half && layout == 1) {
             if constexpr (MM == 8192)  // two transforms of 4096 per column, one per block
-                hipLaunchKernelGGL((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx), dim3(MM / 32),
+                launch_kernel((k_col_split<MM / 2, HF, ST, LayTile>), dim3(mx), dim3(MM / 32),
                                    0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw,
                                    LayTile{ny});
             else
-                hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayTile>), dim3(items),
+                launch_kernel((k_col<MM, true, HF, ST, LayTile>), dim3(items),
                                    dim3(C::THREADS), 0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf,
                                    hscale, tw, LayTile{ny});
         } else if (half) {
-            hipLaunchKernelGGL((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
+            launch_kernel((k_col<MM, true, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
                                0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw, LayRow{mx});
         } else if constexpr (std::is_same_v<ST, StF32>) {
-            hipLaunchKernelGGL((k_col<MM, false, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
+            launch_kernel((k_col<MM, false, HF, ST, LayRow>), dim3(items), dim3(C::THREADS),
                                0, s, (SE*)buf, ny, mx, 1, (size_t)0, hf, hscale, tw, LayRow{mx});
         } else {
             return hipErrorInvalidValue;
@@ -151,7 +151,7 @@ static hipError_t launch_shifted_prec(void* buf, int ny, int my, int mx, const H
 hipError_t launch_col_asm_shifted(void* buf, int ny, int my, int mx, const AsmScalars& a,
                                   const AsmShift& sh, float* masks, const Storage& st,
                                   const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL(k_band_masks, dim3((mx + my + 255) / 256), dim3(256), 0, s, masks, mx, my,
+    launch_kernel(k_band_masks, dim3((mx + my + 255) / 256), dim3(256), 0, s, masks, mx, my,
                        a.dfx, a.dfy, sh);
     const double sx = a.lam * (0.5 * mx) * a.dfx, sy = a.lam * (0.5 * my) * a.dfy;
     if (sx * sx + sy * sy <= kAsmFastMaxS) {

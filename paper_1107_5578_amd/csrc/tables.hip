@@ -92,14 +92,14 @@ hipError_t launch_fresnel_planes(double2* work, float2* out, const FresnelPlanes
                                  hipStream_t s) {
     if (fp.mx > kChirpMaxM || fp.my > kChirpMaxM) return hipErrorInvalidValue;
     if (fp.analytic) {
-        hipLaunchKernelGGL(k_fresnel_tf, dim3((fp.mx + fp.my + 255) / 256, fp.nz), dim3(256), 0, s,
+        launch_kernel(k_fresnel_tf, dim3((fp.mx + fp.my + 255) / 256, fp.nz), dim3(256), 0, s,
                            out, fp);
         return hipGetLastError();
     }
     const int len = fp.mx + fp.my;
     double2* tw64 = work;
-    hipLaunchKernelGGL(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);
-    hipLaunchKernelGGL(k_chirp_fft, dim3(2, fp.nz), dim3(256), 0, s, (const double2*)tw64, out, fp);
+    launch_kernel(k_twiddles64, dim3((len + 255) / 256), dim3(256), 0, s, tw64, fp.mx, fp.my);
+    launch_kernel(k_chirp_fft, dim3(2, fp.nz), dim3(256), 0, s, (const double2*)tw64, out, fp);
     return hipGetLastError();
 }
 

@@ -252,10 +252,10 @@ hipError_t row_inv_z_t(const void* zbuf, const ZChunk& zc, int nx, int ny, int m
         if (half) {
             auto k = k_row_inv_t<MM, true, OutTable, ST>;
             const int g = resident_blocks(k, C::THREADS, items);
-            hipLaunchKernelGGL(k, dim3(g), dim3(C::THREADS), 0, s, (const SE*)zbuf, t, nx, ny,
+            launch_kernel(k, dim3(g), dim3(C::THREADS), 0, s, (const SE*)zbuf, t, nx, ny,
                                zc.nz, zplane, scale, dyn_inv, tw);
         } else if constexpr (std::is_same_v<ST, StF32>) {
-            hipLaunchKernelGGL((k_row_inv_t<MM, false, OutTable, ST>), dim3(items),
+            launch_kernel((k_row_inv_t<MM, false, OutTable, ST>), dim3(items),
                                dim3(C::THREADS), 0, s, (const SE*)zbuf, t, nx, ny, zc.nz, zplane,
                                scale, dyn_inv, tw);
         } else {
@@ -274,10 +274,10 @@ hipError_t col_z_asm_t(const void* spec, void* zbuf, int ny, int my, int mx, siz
         using C = ZColCfg<MM>;
         dim3 grid((mx + C::COLS - 1) / C::COLS);
         if (half)
-            hipLaunchKernelGGL((k_col_z_asm<MM, true, ZH, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_col_z_asm<MM, true, ZH, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
         else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_col_z_asm<MM, false, ZH, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_col_z_asm<MM, false, ZH, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
         else
             return hipErrorInvalidValue;
@@ -294,10 +294,10 @@ hipError_t col_z_fresnel_t(const void* spec, void* zbuf, int ny, int my, int mx,
         using C = ZColCfg<MM>;
         dim3 grid((mx + C::COLS - 1) / C::COLS);
         if (half)
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, true, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_col_z_fresnel<MM, true, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
         else if constexpr (std::is_same_v<ST, StF32>)
-            hipLaunchKernelGGL((k_col_z_fresnel<MM, false, ST>), grid, dim3(C::THREADS), 0, s,
+            launch_kernel((k_col_z_fresnel<MM, false, ST>), grid, dim3(C::THREADS), 0, s,
                                (const SE*)spec, (SE*)zbuf, ny, mx, zplane, zs, hscale, tw);
         else
             return hipErrorInvalidValue;
