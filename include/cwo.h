@@ -317,7 +317,8 @@ cwo_status cwo_batch(cwo_ctx* ctx, const cwo_job* jobs, int32_t njobs, void* hip
  * exponent of its largest component: u, then a2 and a1); arithmetic, u and E_k stay
  * FP32 (E_k's sums FP64). Low precision needs the padded form (no CWO_FLAG_NOPAD).
  * Scratch: ny * Mx stored values (Mx = 2nx, or nx with CWO_FLAG_NOPAD), plus
- * iterations * ny * max(1, Mx/1024) doubles for E_k (the rows' error partials). */
+ * iterations * ny * max(1, Mx/1024) + 512 doubles for E_k (the rows' error partials and
+ * those of sum(a2^2)). */
 cwo_status cwo_gs(cwo_ctx* ctx, const cwo_params* p, const float* a1, const float* a2, void* u,
                   int32_t iterations, float* errors, void* hip_stream);
 

@@ -1852,7 +1852,7 @@ cwo_status cwo_gs(cwo_ctx* c, const cwo_params* p, const float* a1, const float*
     double* num = nullptr;
     const size_t nrow = (size_t)g.ny * cwo::gs_partials(g.mx);  // error partials per iteration
     if (errors) {
-        num = (double*)ensure(c, c->ws, c->ws.gsnum, sizeof(double) * ((size_t)iterations * nrow + 1),
+        num = (double*)ensure(c, c->ws, c->ws.gsnum, sizeof(double) * ((size_t)iterations * nrow + cwo::kGsDenParts),
                               &st);
         if (!num) return st;
     }

@@ -261,13 +261,16 @@ __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu
     }
 }
 
-// den = sum(amp^2) in FP64 by one block (deterministic order), then one block per
-// iteration sums its row partials.
-__global__ __launch_bounds__(256) void k_gs_den(const float* __restrict__ amp, double* den,
-                                                long long count) {
+// den = sum(amp^2) in FP64 as kGsDenParts partials, partial b over the contiguous chunk b
+// of the array (per-thread strided sums, then a fixed tree): the same order on every run.
+__global__ __launch_bounds__(256) void k_gs_den(const float* __restrict__ amp,
+                                                double* __restrict__ part, long long count) {
     __shared__ double red[256];
+    const long long chunk = (count + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < count ? lo + chunk : count;
     double t = 0.0;
-    for (long long i = threadIdx.x; i < count; i += 256) {
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
         const double a = amp[i];
         t += a * a;
     }
@@ -277,24 +280,35 @@ __global__ __launch_bounds__(256) void k_gs_den(const float* __restrict__ amp, d
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *den = red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// iteration k's error from its n = ny * P row partials, summed in a fixed order
-__global__ __launch_bounds__(256) void k_gs_errors(const double* __restrict__ num,
-                                                   const double* __restrict__ den,
-                                                   float* __restrict__ errors, int n) {
-    __shared__ double red[256];
-    const int k = blockIdx.x;
+// sum of n values in a fixed order (per-thread strided sums, then a fixed tree); every
+// thread of the block gets the result
+__device__ double block_sum_fixed(const double* __restrict__ v, int n, double* red) {
     double t = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) t += num[(size_t)k * n + i];
+    for (int i = threadIdx.x; i < n; i += 256) t += v[i];
     red[threadIdx.x] = t;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) errors[k] = (float)sqrt(red[0] / *den);
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// iteration k's error from its n = ny * P row partials and the denominator's partials,
+// each summed in a fixed order
+__global__ __launch_bounds__(256) void k_gs_errors(const double* __restrict__ num,
+                                                   const double* __restrict__ den_part,
+                                                   float* __restrict__ errors, int n) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    const double sn = block_sum_fixed(num + (size_t)k * n, n, red);
+    const double sd = block_sum_fixed(den_part, kGsDenParts, red);
+    if (threadIdx.x == 0) errors[k] = (float)sqrt(sn / sd);
 }
 
 // ---- host launchers ------------------------------------------------------------
@@ -360,7 +374,7 @@ int gs_partials(int mx) { return gs_partials_per_row(mx); }
 
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
                             int nx, int ny, int mx, int iters, hipStream_t s) {
-    launch_kernel(k_gs_den, dim3(1), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
+    launch_kernel(k_gs_den, dim3(kGsDenParts), dim3(256), 0, s, amp, den_work, (long long)nx * ny);
     launch_kernel(k_gs_errors, dim3(iters), dim3(256), 0, s, num, (const double*)den_work,
                        errors, ny * gs_partials_per_row(mx));
     return hipGetLastError();

@@ -172,7 +172,8 @@ hipError_t launch_row_gs(void* spec, const float* amp, float2* out, double* num,
                          int mx, const GsScale& gsc, const float2* tw, hipStream_t s);
 int gs_partials(int mx);
 // errors[k] = sqrt(sum of num[k*ny*P ..] over the ny*P partials / sum(amp^2)), k < iters,
-// P = gs_partials(mx); den_work holds 1 double.
+// P = gs_partials(mx); den_work holds kGsDenParts doubles (the denominator's partials).
+constexpr int kGsDenParts = 512;
 hipError_t launch_gs_errors(const double* num, const float* amp, double* den_work, float* errors,
                             int nx, int ny, int mx, int iters, hipStream_t s);
 
