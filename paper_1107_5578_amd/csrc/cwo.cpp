@@ -981,13 +981,20 @@ size_t growth(const Workspace& ws, const WsNeed& need) {
 // HBM budget: the input and output fields of every admitted, unfinished request, the
 // memory every workspace of the context holds, and what the new batch would add to its
 // slot's workspace, together at most the budget. Idle slots give their workspaces back
-// when memory is short. A free slot takes the head request and the following ones that
-// fit (up to kMaxBatch) as one batch, run back to back on its stream (requests on the same
-// field form a z-stack). Slots run concurrently, so work from different arrivals overlaps
-// on the device. Launching happens outside the queue lock, so submit and poll never wait
-// for kernel launches or allocations.
+// when memory is short. A free slot takes the head request and, from the first kWindow
+// queued requests in arrival order, those of the head's geometry (sizes, pitch, flags,
+// precision) that fit, up to kMaxBatch and kBatchScratch bytes of padded planes, as one
+// batch run on its stream: one launch per pass for the whole batch, a z-stack for requests
+// on one field. Queued requests do not depend on each other (an input is complete when it
+// is submitted), but a request that shares a buffer with an earlier one left in the queue
+// is not taken ahead of it. Every request becomes the head in arrival order, so none waits
+// behind later ones for long. Slots run concurrently, so work from different arrivals
+// overlaps on the device. Launching happens outside the queue lock, so submit and poll
+// never wait for kernel launches or allocations.
 
 constexpr int kMaxBatch = 8;
+constexpr size_t kWindow = 64;
+constexpr size_t kBatchScratch = size_t(1) << 30;
 
 double now_s(const cwo_ctx* c) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - c->t0).count();
@@ -1014,6 +1021,12 @@ size_t held_bytes(cwo_ctx* c) {
 // such a batch is reordered (stably) so that requests of one geometry sit next to each
 // other, those on one field first among them: run_jobs then runs them as shared-launch
 // batches or z-stacks. A batch with a dependence keeps its arrival order.
+// Requests that can share a serving batch's launches: one geometry and storage.
+bool same_geometry(const cwo_job& a, const cwo_job& b) {
+    return a.p.nx == b.p.nx && a.p.ny == b.p.ny && a.p.dx == b.p.dx && a.p.dy == b.p.dy &&
+           a.p.flags == b.p.flags && a.p.precision == b.p.precision;
+}
+
 void group_batch(std::vector<cwo_job>& batch, std::vector<uint64_t>& ids) {
     const size_t n = batch.size();
     for (size_t i = 0; i < n; ++i)
@@ -1070,11 +1083,34 @@ void serve_loop(cwo_ctx* c) {
             if (!sl.running.empty() || c->queue.empty()) continue;
             std::vector<cwo_job> batch;
             std::vector<uint64_t> ids;
-            size_t io = 0;
+            std::vector<size_t> taken;  // queue positions of the batch, ascending
+            size_t io = 0, planes = 0;
             bool trimmed = false;
-            for (size_t k = 0; k < c->queue.size() && (int)batch.size() < kMaxBatch; ++k) {
+            const cwo_job& head = c->tickets[c->queue.front()].job;
+            const bool head_batchable = batchable(head);
+            for (size_t k = 0; k < c->queue.size() && k < kWindow && (int)batch.size() < kMaxBatch;
+                 ++k) {
                 const uint64_t id = c->queue[k];
                 const Ticket& tk = c->tickets[id];
+                if (k > 0) {
+                    // a shared-launch batch, or a z-stack on the head's field
+                    if (!(head_batchable && same_geometry(head, tk.job) && batchable(tk.job)) &&
+                        !same_group(head, tk.job))
+                        continue;
+                    // not ahead of an earlier request left in the queue that shares a buffer
+                    bool clash = false;
+                    for (size_t e = 0, t = 0; e < k && !clash; ++e) {
+                        if (t < taken.size() && taken[t] == e) {
+                            ++t;
+                            continue;
+                        }
+                        const cwo_job& o = c->tickets[c->queue[e]].job;
+                        clash = o.out == tk.job.in || o.out == tk.job.out || o.in == tk.job.out;
+                    }
+                    if (clash) continue;
+                    const size_t pb = footprint(&tk.job.p) - io_bytes(&tk.job.p);
+                    if (planes + pb > kBatchScratch) break;
+                }
                 batch.push_back(tk.job);
                 // the memory of the batch as it will run (grouped by geometry)
                 std::vector<cwo_job> grouped = batch;
@@ -1099,7 +1135,9 @@ void serve_loop(cwo_ctx* c) {
                     break;  // FIFO: the next request waits for memory
                 }
                 io += io_bytes(&tk.job.p);
+                planes += footprint(&tk.job.p) - io_bytes(&tk.job.p);
                 ids.push_back(id);
+                taken.push_back(k);
             }
             if (batch.empty()) {
                 // the head does not fit; with nothing running and nothing left to give back it
@@ -1120,7 +1158,7 @@ void serve_loop(cwo_ctx* c) {
                 }
                 break;
             }
-            for (size_t k = 0; k < ids.size(); ++k) c->queue.pop_front();
+            for (size_t t = taken.size(); t-- > 0;) c->queue.erase(c->queue.begin() + taken[t]);
             group_batch(batch, ids);
             const double t = now_s(c);
             std::vector<hipEvent_t> waits;

@@ -124,6 +124,49 @@ def test_alone_vs_mix_serving_sizes(torch):
         alone.close()
 
 
+def test_window_batches_one_geometry(torch):
+    """With every slot busy (four 4096^2 requests of different pitches, one per slot),
+    interleaved requests of two sizes queue up; a freed slot takes the head request and the
+    queued requests of its geometry as one batch, so requests of one size share a few start
+    times, and every result equals its synchronous call."""
+    from paper_1107_5578_amd import cwo
+    server = cwo.Context(0, hbm_budget_bytes=8 << 30)
+    alone = cwo.Context(0)
+    try:
+        big = torch.from_numpy(W.uniform_random_field(4096, 31)).cuda()
+        bouts = [torch.empty_like(big) for _ in range(4)]
+        reqs = []
+        for k in range(8):
+            for n in (256, 512):
+                u = torch.from_numpy(W.uniform_random_field(n, 9100 + 10 * n + k)).cuda()
+                kind = "asm" if k % 3 else "fresnel"
+                reqs.append((kind, u, dict(dx=8e-6, wavelength=532e-9, z=0.05 + 0.01 * k)))
+        outs = [torch.empty_like(u) for _, u, _ in reqs]
+        torch.cuda.synchronize()
+        note("serving 4 blockers and %d interleaved 256^2 / 512^2 requests" % len(reqs))
+        bt = [server.submit("asm", big, o, dx=p, wavelength=532e-9, z=0.3)
+              for o, p in zip(bouts, (8e-6, 9e-6, 10e-6, 11e-6))]
+        tickets = [server.submit(kind, u, o, **kw) for (kind, u, kw), o in zip(reqs, outs)]
+        server.drain()
+        for t in bt:
+            assert server.poll(t) == cwo.DONE
+        starts = {256: set(), 512: set()}
+        for t, (kind, u, kw), o in zip(tickets, reqs, outs):
+            assert server.poll(t) == cwo.DONE
+            starts[u.shape[0]].add(server.info(t)["t_start"])
+            fn = alone.asm if kind == "asm" else alone.fresnel
+            ref = fn(u, kw["dx"], kw["dx"], kw["wavelength"], kw["z"])
+            torch.cuda.synchronize()
+            err = D.rel_l2(o.cpu().numpy(), ref.cpu().numpy().astype(np.complex128))
+            assert err <= 1e-6, (u.shape, kind, err)
+        note("distinct start times per size: %s" % {n: len(v) for n, v in starts.items()})
+        # eight requests per size; at most eight per batch
+        assert len(starts[256]) <= 3 and len(starts[512]) <= 3, starts
+    finally:
+        server.close()
+        alone.close()
+
+
 def test_memory_held_within_budget(torch):
     """Held device memory never exceeds the budget: 4096^2 requests (each 512 MiB of fields
     and scratch) and then 512^2 requests through a 1.25 GiB budget; idle slots give their
