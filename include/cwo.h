@@ -360,11 +360,14 @@ cwo_status cwo_pls_field(cwo_ctx* ctx, const cwo_pls_params* p, const float* poi
  * budget: the input and output fields of every admitted, unfinished job, all memory the
  * context holds, and what the new batch adds to its slot's scratch together stay within the
  * budget (idle slots free their scratch first when memory is short). A free slot takes the
- * head job and, from the first 64 queued jobs in arrival order, the jobs of its geometry
- * (sizes, pitch, flags, storage) that fit, up to 8 and 1 GiB of padded planes, as one batch
+ * head job and, from the first 256 queued jobs in arrival order, the jobs of its geometry
+ * (sizes, pitch, flags, storage) that fit, up to 8 and 512 MiB of padded planes, as one batch
  * on its stream: one launch per pass for the batch (complex64 jobs on one field form a
  * z-stack). A job that shares a buffer with an earlier queued job is not taken ahead of it;
- * every job becomes the head in arrival order. Requests that arrive while others run are
+ * every job becomes the head in arrival order (the environment variables
+ * CWO_SERVE_MAX_BATCH, CWO_SERVE_WINDOW, CWO_SERVE_BATCH_MIB and CWO_SERVE_POLL_US, read
+ * by cwo_create, change the 8 jobs, the window of 256, the 512 MiB and the scheduler's
+ * 5 us polling interval while slots run). Requests that arrive while others run are
  * admitted as slots and memory free up, and their work overlaps on the device. Submit and
  * poll never wait for the scheduler's launches or allocations.
  * Footprint of a job (reported by cwo_ticket_info): its input and output fields plus its
