@@ -259,10 +259,11 @@ def serve_bench(ctx_cls, torch, W, dev, count, budget=8 << 30, rates=(0.5, 0.8, 
     z ~ U[0.01, 1] m, wavelength in {473, 532, 633} nm, 8 um pitch) through cwo_submit /
     cwo_poll under an HBM budget. Every request reads a field of its own: 10k distinct
     fields do not fit, so each size has a ring of FIELD_RING distinct seeded fields and
-    successive requests of one size take successive fields. A serving batch takes at most 8
-    requests of one size, the oldest queued ones of that size, so with a ring of 8 no batch
-    holds two requests on one field and none can be merged into a z-stack. Outputs rotate through a ring per size (a buffer is
-    reused only after its previous request is done)."""
+    successive requests of one size take successive fields. A serving batch takes requests
+    of one size, the oldest queued ones of that size, at most 8 of them (the library's
+    default; CWO_SERVE_MAX_BATCH must stay unset or at most FIELD_RING), so no batch holds
+    two requests on one field and none can be merged into a z-stack. Outputs rotate through
+    a ring per size (a buffer is reused only after its previous request is done)."""
     FIELD_RING = 8
     reqs = W.serving_requests(count, 1.0, seed=5)
     sizes = sorted({r.n for r in reqs})
