@@ -136,7 +136,7 @@ struct GsTileChunks {
     static_assert(CPT * C::THREADS == (M / kTileW) * PER_TILE, "chunks");
 };
 
-template <int M, class ST, int RPB>
+template <int M, class ST, int RPB, int PF>
 __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) void k_row_gs_tile(
     typename ST::E* __restrict__ spec, const float* __restrict__ amp, float2* __restrict__ out,
     double* __restrict__ num, int nx, int ny, float scale, const float* __restrict__ dyn_inv,
@@ -156,10 +156,10 @@ __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu
     const ItemRange ir = xcd_items(blockIdx.x, gridDim.x, groups);
     TwCache<M, E> twc;
     twc.load(j, tw);
-    auto load = [&](int g, PK (&d)[K::CPT], int tl) {
+    auto load = [&](int g, PK (&d)[K::CPT], int tl, int lo, int hi) {
         const int y0 = g * C::RPB;
 #pragma unroll
-        for (int k = 0; k < K::CPT; ++k) {
+        for (int k = lo; k < hi; ++k) {
             const int c = tl + k * C::THREADS;
             const int t = c / K::PER_TILE, q = c - t * K::PER_TILE;
             d[k] = *reinterpret_cast<const PK*>(spec + ((size_t)t * ny + y0) * kTileW + q * K::CE);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu
     float acur[NL];
     int g = ir.first;
     if (g >= ir.end) return;  // the whole block (ir is uniform)
-    load(g, cur, tid);
+    load(g, cur, tid, 0, K::CPT);
     load_amp(g, acur, j);
     for (;;) {
         const bool more = g + ir.step < ir.end;
@@ -200,7 +200,9 @@ __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu
             v[0][r] = lds[(x / kTileW) * C::TS + sub * kTileW + (x % kTileW)];
         }
         lds_barrier();
-        if (more) load(g + ir.step, cur, tt);
+        // the next group's first PF chunks are loaded during the inverse transform, the rest
+        // after the constraint (fewer registers held through the transform)
+        if (more) load(g + ir.step, cur, tt, 0, PF);
         const int y0 = g * C::RPB, row = y0 + sub;
         fft<M, E, 1, INV>(v, my_lds, jt, twc);
         double acc = 0.0;
@@ -227,6 +229,10 @@ __global__ __launch_bounds__((GsTileCfg<M, RPB>::THREADS)) __attribute__((amdgpu
             }
         }
         if (more) load_amp(g + ir.step, acur, jt);
+        if constexpr (PF < K::CPT) {
+            asm volatile("" ::: "memory");  // these loads stay after the inverse transform
+            if (more) load(g + ir.step, cur, tt, PF, K::CPT);
+        }
         if (num) row_partials<T>(acc, num, row, jt, true);
         if (out) {
             float2* orow = out + (size_t)row * nx;
@@ -330,7 +336,11 @@ hipError_t row_gs_t(void* spec, const float* amp, float2* out, double* num, int 
                 constexpr int RPB = MM == 4096 ? 1 : 2;
                 using C = GsTileCfg<MM, RPB>;
                 if (ny % C::RPB != 0) return hipErrorInvalidValue;
-                auto k = k_row_gs_tile<MM, ST, RPB>;
+                // complex64 rows of 4096: half the next group's chunks in flight during the
+                // inverse transform (all of them spilled 28 bytes of registers per lane)
+                using K = GsTileChunks<MM, RPB, SE>;
+                constexpr int PF = (MM == 4096 && std::is_same_v<ST, StF32>) ? K::CPT / 2 : K::CPT;
+                auto k = k_row_gs_tile<MM, ST, RPB, PF>;
                 launch_kernel(k, dim3(resident_blocks(k, C::THREADS, ny / C::RPB)),
                                    dim3(C::THREADS), 0, s, (SE*)spec, amp, out, num, nx, ny,
                                    scale, dyn_inv, fwd_scale, dyn_fwd, tw);
