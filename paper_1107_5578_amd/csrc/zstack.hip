@@ -203,6 +203,10 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
     twc.load(j, tw);
     const int ntiles = (ny + C::COLS - 1) / C::COLS;
     auto item = [&](int it) {
+        // the thread's index, opaque to the compiler in each item of the persistent loop: the
+        // addresses derived from it are recomputed per item instead of held (or spilled)
+        int jt = j;
+        asm volatile("" : "+v"(jt));
         const int pl = it / ntiles, tile = it - pl * ntiles;
         const int y0 = (tile * C::PAIRS + pair) * P;  // first row of this thread (ny is even)
         const bool active = y0 < ny;
@@ -210,18 +214,20 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) __attribute__((amdgpu_waves_per
         float2 v[P][E];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            const PK t = *reinterpret_cast<const PK*>(base + (size_t)(j + r * T) * ny);
+            const PK t = *reinterpret_cast<const PK*>(base + (size_t)(jt + r * T) * ny);
 #pragma unroll
             for (int p = 0; p < P; ++p) v[p][r] = ST::dec(t.e[p]);
         }
-        fft<M, E, P, INV, C::SPLIT>(v, my_lds, j, twc);
+        fft<M, E, P, INV, C::SPLIT>(v, my_lds, jt, twc);
+        int jo = j;
+        asm volatile("" : "+v"(jo));
         if (active) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const size_t base = (size_t)(y0 + p) * nx;
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
-                    const int x = j + r * T;
+                    const int x = jo + r * T;
                     if (HALF ? (r < E / 2) : (x < nx))
                         outs.put(pl, base + x, make_float2(v[p][r].x * scale, v[p][r].y * scale));
                 }
